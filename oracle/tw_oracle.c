@@ -1,0 +1,427 @@
+/*
+ * CPU oracle for exact treewidth by elimination orderings.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg do.  It shares no code, header, table or constant with the
+ * HIP path.
+ *
+ * Everything here is deliberately plain and slow:
+ *
+ *   - Q(S,v) and its size follow the definition in §2 (Preliminaries): the
+ *     vertices outside S that v reaches by paths whose internal vertices all
+ *     lie in S.  The size is computed by the stack-based depth-first search of
+ *     Listing 1 (§3.1) over adjacency lists, with v itself marked visited
+ *     before the search starts so it is never counted (reading: v is not a
+ *     member of Q(S,v)).
+ *
+ *   - O1, the subset dynamic programme (§1 and §2: eliminating a set S gives
+ *     the same intermediate graph whatever the order, so a Held-Karp style
+ *     recurrence over subsets works):
+ *        TW(empty) = 0,
+ *        TW(S) = min over v in S of max(TW(S - v), |Q(S - v, v)|),
+ *     and tw(G) = TW(V).
+ *
+ *   - O2, brute force over all n! orders with the width of each order found by
+ *     explicit fill-in (§2, the alternative view: eliminating v removes it and
+ *     turns its neighbourhood into a clique; the width is the largest degree
+ *     met).  A second, independent definition used to pin O1.
+ *
+ *   - O4, the level-by-level search of Listing 1 (§3.1) for one bound k: every
+ *     set S of the input list is extended by every vertex v outside S whose
+ *     degree |Q(S,v)| is at most k; duplicates are removed exactly (sort and
+ *     unique, not a Bloom filter).
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC -o libtworacle.so tw_oracle.c
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MAXN 64
+
+typedef struct {
+    int n;
+    int deg[MAXN];
+    int nbr[MAXN][MAXN]; /* adjacency lists, ascending */
+} adjlist;
+
+static void build_lists(int n, const uint64_t *rows, adjlist *g)
+{
+    g->n = n;
+    for (int u = 0; u < n; u++) {
+        g->deg[u] = 0;
+        for (int w = 0; w < n; w++)
+            if ((rows[u] >> w) & 1ULL)
+                g->nbr[u][g->deg[u]++] = w;
+    }
+}
+
+/* |Q(S,v)| by the depth-first search of Listing 1 (§3.1).  v must lie outside
+ * S.  Vertices of S that are reached are pushed and explored further; every
+ * other newly reached vertex is counted once. */
+static int q_degree(const adjlist *g, uint64_t S, int v)
+{
+    unsigned char visited[MAXN];
+    int stack[MAXN];
+    int top = 0, degree = 0;
+    memset(visited, 0, sizeof visited);
+    visited[v] = 1;
+    stack[top++] = v;
+    while (top > 0) {
+        int u = stack[--top];
+        for (int t = 0; t < g->deg[u]; t++) {
+            int w = g->nbr[u][t];
+            if (visited[w])
+                continue;
+            visited[w] = 1;
+            if ((S >> w) & 1ULL)
+                stack[top++] = w;
+            else
+                degree++;
+        }
+    }
+    return degree;
+}
+
+int tworacle_q_degree(int n, const uint64_t *rows, uint64_t S, int v)
+{
+    adjlist g;
+    if (n < 1 || n > MAXN || v < 0 || v >= n || ((S >> v) & 1ULL))
+        return -1;
+    build_lists(n, rows, &g);
+    return q_degree(&g, S, v);
+}
+
+static int popcount64(uint64_t x)
+{
+    int c = 0;
+    while (x) {
+        x &= x - 1;
+        c++;
+    }
+    return c;
+}
+
+/* O1: fills tw_table[S] = TW(S) for all 2^n subsets S, returns TW(V).
+ * Subsets are processed one cardinality at a time; within a cardinality every
+ * entry depends only on the previous one, so those entries are independent. */
+int tworacle_subset_dp(int n, const uint64_t *rows, uint8_t *tw_table, int nthreads)
+{
+    adjlist g;
+    if (n < 1 || n > 30)
+        return -1;
+    build_lists(n, rows, &g);
+    const int64_t total = (int64_t)1 << n;
+    tw_table[0] = 0;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+    for (int c = 1; c <= n; c++) {
+#pragma omp parallel for schedule(dynamic, 4096)
+        for (int64_t S = 1; S < total; S++) {
+            if (popcount64((uint64_t)S) != c)
+                continue;
+            int best = 255;
+            for (int v = 0; v < n; v++) {
+                if (!(((uint64_t)S >> v) & 1ULL))
+                    continue;
+                uint64_t R = (uint64_t)S & ~(1ULL << v);
+                int d = q_degree(&g, R, v);
+                int w = tw_table[R] > d ? tw_table[R] : d;
+                if (w < best)
+                    best = w;
+            }
+            tw_table[S] = (uint8_t)best;
+        }
+    }
+    return tw_table[total - 1];
+}
+
+/* Level i of the bound-k search read off an O1 table: all S with |S| = i and
+ * TW(S) <= k, in ascending order.  Returns the count (or -1 if it exceeds cap;
+ * out may be NULL to only count). */
+int64_t tworacle_frontier_from_table(int n, const uint8_t *tw_table, int i, int k,
+                                     uint64_t *out, int64_t cap)
+{
+    const int64_t total = (int64_t)1 << n;
+    int64_t cnt = 0;
+    for (int64_t S = 0; S < total; S++) {
+        if (popcount64((uint64_t)S) == i && tw_table[S] <= k) {
+            if (out) {
+                if (cnt >= cap)
+                    return -1;
+                out[cnt] = (uint64_t)S;
+            }
+            cnt++;
+        }
+    }
+    return cnt;
+}
+
+/* Width of an elimination order by explicit fill-in (§2, alternative view).
+ * Returns -1 if order is not a permutation of 0..n-1. */
+static int fill_in_width(int n, const unsigned char adj0[MAXN][MAXN], const int *order)
+{
+    unsigned char adj[MAXN][MAXN];
+    unsigned char alive[MAXN];
+    memcpy(adj, adj0, sizeof adj);
+    for (int u = 0; u < n; u++)
+        alive[u] = 1;
+    int width = 0;
+    for (int t = 0; t < n; t++) {
+        int v = order[t];
+        int nb[MAXN], d = 0;
+        for (int u = 0; u < n; u++)
+            if (alive[u] && u != v && adj[v][u])
+                nb[d++] = u;
+        if (d > width)
+            width = d;
+        for (int a = 0; a < d; a++)
+            for (int b = 0; b < d; b++)
+                if (a != b)
+                    adj[nb[a]][nb[b]] = 1;
+        alive[v] = 0;
+    }
+    return width;
+}
+
+static void build_matrix(int n, const uint64_t *rows, unsigned char adj[MAXN][MAXN])
+{
+    memset(adj, 0, sizeof(unsigned char) * MAXN * MAXN);
+    for (int u = 0; u < n; u++)
+        for (int w = 0; w < n; w++)
+            adj[u][w] = (unsigned char)((rows[u] >> w) & 1ULL);
+}
+
+int tworacle_order_width(int n, const uint64_t *rows, const int32_t *order)
+{
+    unsigned char adj[MAXN][MAXN];
+    unsigned char seen[MAXN];
+    int ord[MAXN];
+    if (n < 1 || n > MAXN)
+        return -1;
+    memset(seen, 0, sizeof seen);
+    for (int t = 0; t < n; t++) {
+        if (order[t] < 0 || order[t] >= n || seen[order[t]])
+            return -1;
+        seen[order[t]] = 1;
+        ord[t] = order[t];
+    }
+    build_matrix(n, rows, adj);
+    return fill_in_width(n, adj, ord);
+}
+
+/* O2: minimum fill-in width over all n! orders (lexicographic enumeration).
+ * best_order (nullable) receives the first order reaching the minimum. */
+int tworacle_brute_force(int n, const uint64_t *rows, int32_t *best_order)
+{
+    unsigned char adj[MAXN][MAXN];
+    int p[MAXN];
+    if (n < 1 || n > 10)
+        return -1;
+    build_matrix(n, rows, adj);
+    for (int t = 0; t < n; t++)
+        p[t] = t;
+    int best = n;
+    for (;;) {
+        int w = fill_in_width(n, adj, p);
+        if (w < best) {
+            best = w;
+            if (best_order)
+                for (int t = 0; t < n; t++)
+                    best_order[t] = p[t];
+        }
+        /* next permutation in lexicographic order */
+        int a = n - 2;
+        while (a >= 0 && p[a] > p[a + 1])
+            a--;
+        if (a < 0)
+            break;
+        int b = n - 1;
+        while (p[b] < p[a])
+            b--;
+        int tmp = p[a];
+        p[a] = p[b];
+        p[b] = tmp;
+        for (int l = a + 1, r = n - 1; l < r; l++, r--) {
+            tmp = p[l];
+            p[l] = p[r];
+            p[r] = tmp;
+        }
+    }
+    return best;
+}
+
+/* LSD radix sort of 64-bit keys, 16 bits per pass (tmp has the same size). */
+static void radix_sort(uint64_t *a, uint64_t *tmp, int64_t cnt)
+{
+    static int64_t hist[1 << 16];
+    uint64_t all_or = 0;
+    for (int64_t t = 0; t < cnt; t++)
+        all_or |= a[t];
+    for (int shift = 0; shift < 64; shift += 16) {
+        if (((all_or >> shift) & 0xFFFFULL) == 0)
+            continue;
+        memset(hist, 0, sizeof hist);
+        for (int64_t t = 0; t < cnt; t++)
+            hist[(a[t] >> shift) & 0xFFFF]++;
+        int64_t sum = 0;
+        for (int d = 0; d < (1 << 16); d++) {
+            int64_t h = hist[d];
+            hist[d] = sum;
+            sum += h;
+        }
+        for (int64_t t = 0; t < cnt; t++)
+            tmp[hist[(a[t] >> shift) & 0xFFFF]++] = a[t];
+        memcpy(a, tmp, (size_t)cnt * sizeof(uint64_t));
+    }
+}
+
+/* O4, one level of Listing 1 (§3.1) for the bound k: every S of in[] is
+ * extended by every v outside S with |Q(S,v)| <= k; the successors are sorted
+ * and duplicates removed.  out[] receives the distinct successors in ascending
+ * order.  Returns their number, -1 on a bad argument or -2 if out_cap is too
+ * small.  *generated (nullable) receives the number of feasible (S,v) pairs,
+ * *candidates (nullable) the number of (S,v) pairs tried. */
+int64_t tworacle_bfs_level(int n, const uint64_t *rows, int k, const uint64_t *in,
+                           int64_t in_count, uint64_t *out, int64_t out_cap,
+                           int64_t *generated, int64_t *candidates, int nthreads)
+{
+    adjlist g;
+    if (n < 1 || n > MAXN || in_count < 0)
+        return -1;
+    build_lists(n, rows, &g);
+    const uint64_t all = n == 64 ? ~0ULL : ((1ULL << n) - 1);
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+    int nt = omp_get_max_threads();
+#else
+    int nt = 1;
+#endif
+    uint64_t **buf = calloc((size_t)nt, sizeof(uint64_t *));
+    int64_t *len = calloc((size_t)nt, sizeof(int64_t));
+    int64_t *capb = calloc((size_t)nt, sizeof(int64_t));
+    int64_t *tried = calloc((size_t)nt, sizeof(int64_t));
+    int fail = 0;
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+        int tid = omp_get_thread_num();
+#else
+        int tid = 0;
+#endif
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t s = 0; s < in_count; s++) {
+            uint64_t S = in[s];
+            for (int v = 0; v < n; v++) {
+                if ((S >> v) & 1ULL)
+                    continue;
+                tried[tid]++;
+                if (q_degree(&g, S, v) <= k) {
+                    if (len[tid] == capb[tid]) {
+                        int64_t nc = capb[tid] ? capb[tid] * 2 : 4096;
+                        uint64_t *nb = realloc(buf[tid], (size_t)nc * sizeof(uint64_t));
+                        if (!nb) {
+                            fail = 1;
+                            continue;
+                        }
+                        buf[tid] = nb;
+                        capb[tid] = nc;
+                    }
+                    buf[tid][len[tid]++] = (S | (1ULL << v)) & all;
+                }
+            }
+        }
+    }
+    int64_t total = 0, ntried = 0;
+    for (int t = 0; t < nt; t++) {
+        total += len[t];
+        ntried += tried[t];
+    }
+    int64_t result = -1;
+    uint64_t *all_keys = NULL, *tmp = NULL;
+    if (!fail) {
+        all_keys = malloc((size_t)(total ? total : 1) * sizeof(uint64_t));
+        tmp = malloc((size_t)(total ? total : 1) * sizeof(uint64_t));
+    }
+    if (all_keys && tmp) {
+        int64_t pos = 0;
+        for (int t = 0; t < nt; t++) {
+            if (len[t])
+                memcpy(all_keys + pos, buf[t], (size_t)len[t] * sizeof(uint64_t));
+            pos += len[t];
+            free(buf[t]);
+            buf[t] = NULL;
+        }
+        radix_sort(all_keys, tmp, total);
+        int64_t u = 0;
+        for (int64_t t = 0; t < total; t++)
+            if (t == 0 || all_keys[t] != all_keys[t - 1])
+                all_keys[u++] = all_keys[t];
+        if (u > out_cap) {
+            result = -2;
+        } else {
+            if (u)
+                memcpy(out, all_keys, (size_t)u * sizeof(uint64_t));
+            result = u;
+        }
+        if (generated)
+            *generated = total;
+        if (candidates)
+            *candidates = ntried;
+    }
+    for (int t = 0; t < nt; t++)
+        free(buf[t]);
+    free(all_keys);
+    free(tmp);
+    free(buf);
+    free(len);
+    free(capb);
+    free(tried);
+    return result;
+}
+
+/* Number of feasible (S,v) pairs over a list of states, without storing them
+ * (used to time the oracle on a bounded sample). */
+int64_t tworacle_count_feasible(int n, const uint64_t *rows, int k, const uint64_t *in,
+                                int64_t in_count, int64_t *candidates, int nthreads)
+{
+    adjlist g;
+    if (n < 1 || n > MAXN)
+        return -1;
+    build_lists(n, rows, &g);
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+    int64_t feas = 0, tried = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : feas, tried)
+    for (int64_t s = 0; s < in_count; s++) {
+        uint64_t S = in[s];
+        for (int v = 0; v < n; v++) {
+            if ((S >> v) & 1ULL)
+                continue;
+            tried++;
+            if (q_degree(&g, S, v) <= k)
+                feas++;
+        }
+    }
+    if (candidates)
+        *candidates = tried;
+    return feas;
+}
+
+int tworacle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
