@@ -1,0 +1,160 @@
+/*
+ * tw.h — exact treewidth on AMD MI355X (gfx950): the level-synchronous search
+ * over elimination-ordering states of van der Zanden & Bodlaender,
+ * "Computing Treewidth on the GPU" (arXiv 1709.09990).
+ *
+ * Definitions used throughout (paper §2 and §3.1):
+ *   - A graph has n <= 64 vertices 0..n-1, given as n adjacency rows: bit j of
+ *     adj[i] is set iff {i, j} is an edge.  Rows must be symmetric with no
+ *     self-loops and no bits at positions >= n.
+ *   - A state is a vertex set S, stored as a bitmask (32-bit keys on the device
+ *     when n <= 32, 64-bit otherwise; always uint64_t across this interface).
+ *   - Q(S, v), for v outside S, is the set of vertices outside S and other than
+ *     v that v reaches by paths whose internal vertices all lie in S (§2).
+ *     |Q(S, v)| is the degree of v once S has been eliminated.
+ *   - For a bound k, level 0 is {empty set}; level i+1 holds every S + {v}
+ *     with S in level i, v not in S and |Q(S, v)| <= k, each set once
+ *     (Listing 1, §3.1; duplicates removed exactly, §3.2).
+ *   - decide(k) is YES iff level L(k) = max(0, n-k-1) is non-empty: the last
+ *     k+1 vertices can go in any order (third optimisation of §3.1).
+ *   - tw(G) = the smallest k with decide(k) = YES.
+ *
+ * All functions are extern "C" and never throw.  Every array argument is a
+ * host pointer owned by the caller unless stated otherwise; the library copies
+ * what it needs during the call and holds no caller pointer afterwards.
+ * Device memory (frontiers, hash tables) belongs to the context and persists
+ * between calls until tw_ctx_destroy.  A context serves one host thread at a
+ * time; calls return after every output has been written.
+ *
+ * Errors are returned, never hidden: no answer is ever truncated.  If the
+ * device memory needed by a level cannot be obtained even after regrowing, the
+ * call fails with TW_ENOMEM (or TW_ECAPACITY when a caller-imposed limit is
+ * hit), and the message is available from tw_last_error.
+ */
+#ifndef TW_H
+#define TW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TW_OK = 0,
+    TW_EINVAL = 1,    /* bad argument: graph not simple/symmetric, n outside 1..64, k < 0, NULL output */
+    TW_ENOMEM = 2,    /* device or host memory could not be obtained */
+    TW_EDEVICE = 3,   /* HIP runtime error, or an internal consistency check failed */
+    TW_ECAPACITY = 4  /* a level needs more states than options.max_states allows */
+} tw_status;
+
+/* Duplicate removal between levels (§3.2). */
+enum {
+    TW_DEDUP_EXACT = 0, /* open-addressing hash table in HBM, atomic compare-and-swap (default) */
+    TW_DEDUP_BLOOM = 1  /* Bloom filter, 17 probes by double hashing (§3.2); a NO answer is then not certified */
+};
+
+/* Choice of the bounds k tried by tw_solve / tw_solve_batch (§3.1). */
+enum {
+    TW_K_ASCENDING = 0, /* k = minor-min-width lower bound (§3.3), then k+1, ... until YES */
+    TW_K_LEARNED = 1    /* start from a predicted k; YES at t is certified by NO at t-1 or t = lower bound */
+};
+
+/* A graph: n rows, host pointer, caller-owned. */
+typedef struct {
+    uint32_t n;
+    const uint64_t *adj;
+} tw_graph;
+
+/* Context options.  Zero-initialise, set struct_size = sizeof(tw_options),
+ * then change what you need. */
+typedef struct {
+    size_t struct_size;
+    int device;               /* HIP device ordinal */
+    void *stream;             /* hipStream_t to launch on, or NULL for a stream the context creates */
+    int dedup;                /* TW_DEDUP_EXACT or TW_DEDUP_BLOOM */
+    float load_factor;        /* target hash-table load in (0, 0.9]; 0 picks the default 0.5 */
+    int k_policy;             /* TW_K_ASCENDING or TW_K_LEARNED */
+    const char *weights_path; /* learned policy weights (TW_K_LEARNED only) */
+    uint64_t max_states;      /* cap on states per level (0 = limited only by device memory) */
+    uint64_t capacity_override; /* test hook: first guess of every level's size (0 = estimate); a
+                                   small value forces the overflow -> regrow -> replay path */
+    int timing;               /* 1: time every expansion launch with HIP events (tw_stats.kernel_*) */
+} tw_options;
+
+/* Counters of one call (summed over every bound k and level it ran). */
+typedef struct {
+    uint64_t states_expanded; /* sum of |level i| over the levels expanded */
+    uint64_t expansions;      /* candidate (S, v) pairs: sum of |level i| * (n - i) */
+    uint64_t successors;      /* feasible (S, v) pairs generated (before duplicate removal) */
+    uint64_t unique;          /* distinct states written: sum of |level i+1| */
+    uint64_t peak_frontier;   /* largest level met */
+    uint32_t decisions;       /* bounds k tried */
+    uint32_t levels;          /* levels expanded */
+    uint32_t retries;         /* levels replayed after an overflow */
+    uint32_t launches;        /* expansion kernel launches (replays included) */
+    double seconds;           /* wall time of the call */
+    double kernel_seconds;    /* summed duration of the expansion launches (options.timing = 1) */
+} tw_stats;
+
+typedef struct tw_ctx tw_ctx;
+
+/* Create a context on options->device (options may be NULL for defaults). */
+tw_status tw_ctx_create(const tw_options *options, tw_ctx **out);
+void tw_ctx_destroy(tw_ctx *ctx);
+
+/* decide(k) of Listing 1 (§3.1): *out_yes = 1 iff tw(G) <= k.  k >= n-1 is
+ * YES without a level.  stats may be NULL. */
+tw_status tw_decide(tw_ctx *ctx, const tw_graph *g, int32_t k, int32_t *out_yes, tw_stats *stats);
+
+/* tw(G) and an elimination order of that width (§2): ascending k from the
+ * minor-min-width bound (§3.3).  out_order[t] is the t-th vertex eliminated;
+ * it must hold n entries.  The order is rebuilt from the last level by
+ * following, for each state, the vertex that created it back to the empty
+ * set, then the k+1 remaining vertices in ascending index; its width is
+ * checked to equal *out_tw before returning. */
+tw_status tw_solve(tw_ctx *ctx, const tw_graph *g, int32_t *out_tw, int32_t *out_order, tw_stats *stats);
+
+/* tw_solve for count graphs of uneven size.  out_tw[count], out_status[count];
+ * out_orders holds the orders back to back (sum of n entries, graph order).
+ * A graph that fails gets its own status; the others still complete.  The
+ * return value is TW_OK unless an argument is invalid or the device failed. */
+tw_status tw_solve_batch(tw_ctx *ctx, const tw_graph *gs, uint32_t count, int32_t *out_tw,
+                         int32_t *out_orders, tw_status *out_status, tw_stats *stats);
+
+/* One level of a bound-k search, as handed to a trace sink. */
+typedef struct {
+    int32_t k;
+    int32_t level;        /* i: this record describes level i (sets of size i) */
+    uint64_t count;       /* |level i| */
+    uint64_t expansions;  /* (S, v) pairs tried to build it: |level i-1| * (n - i + 1) */
+    uint64_t successors;  /* feasible pairs among them */
+    const uint64_t *states; /* the |level i| states, unordered; valid during the callback only */
+    const uint8_t *last_v;  /* for each state, a vertex v with state - {v} in level i-1 */
+} tw_level_record;
+
+/* Test hook: decide(k) with every level copied to the host and handed to
+ * sink (levels 0..L(k), or up to the first empty one). */
+tw_status tw_trace_decide(tw_ctx *ctx, const tw_graph *g, int32_t k,
+                          void (*sink)(const tw_level_record *rec, void *user), void *user,
+                          int32_t *out_yes);
+
+/* Minor-min-width lower bound with the second-smallest-degree improvement
+ * (§3.3): each round takes the lowest-index vertex of minimum degree, deletes
+ * it if isolated, otherwise contracts it into its lowest-index minimum-degree
+ * neighbour; the bound is the largest second-smallest degree met. Host only. */
+tw_status tw_mmw(const tw_graph *g, int32_t *out_lb);
+
+/* Width of an elimination order by fill-in (§2); -1 in *out_width if order is
+ * not a permutation of 0..n-1.  Host only. */
+tw_status tw_order_width(const tw_graph *g, const int32_t *order, int32_t *out_width);
+
+const char *tw_status_str(tw_status s);
+/* Message of the last failure on ctx (empty string if none); valid until the next call. */
+const char *tw_last_error(const tw_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TW_H */

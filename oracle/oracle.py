@@ -72,7 +72,9 @@ def lib():
         L.tworacle_brute_force.argtypes = [ctypes.c_int, u64p, i32p]
         L.tworacle_brute_force.restype = ctypes.c_int
         L.tworacle_bfs_level.argtypes = [ctypes.c_int, u64p, ctypes.c_int, u64p, ctypes.c_int64,
-                                         u64p, ctypes.c_int64, i64p, i64p, ctypes.c_int]
+                                         ctypes.POINTER(u64p), i64p, i64p, ctypes.c_int]
+        L.tworacle_free.argtypes = [ctypes.c_void_p]
+        L.tworacle_free.restype = None
         L.tworacle_bfs_level.restype = ctypes.c_int64
         L.tworacle_count_feasible.argtypes = [ctypes.c_int, u64p, ctypes.c_int, u64p,
                                               ctypes.c_int64, i64p, ctypes.c_int]
@@ -205,19 +207,19 @@ def bfs_level(rows, k: int, frontier: np.ndarray, threads: int = 0):
     a = _rows(rows)
     n = len(a)
     f = np.ascontiguousarray(np.asarray(frontier, dtype=np.uint64))
-    cap = max(1, len(f) * max(1, n))
-    while True:
-        out = np.zeros(cap, dtype=np.uint64)
-        gen = ctypes.c_int64(0)
-        cand = ctypes.c_int64(0)
-        cnt = lib().tworacle_bfs_level(n, _p(a, u64p), int(k), _p(f, u64p), len(f), _p(out, u64p),
-                                       cap, ctypes.byref(gen), ctypes.byref(cand), threads)
-        if cnt == -2:
-            cap *= 2
-            continue
-        if cnt < 0:
-            raise RuntimeError("oracle bfs_level failed")
-        return out[:cnt].copy(), gen.value, cand.value
+    ptr = u64p()
+    gen = ctypes.c_int64(0)
+    cand = ctypes.c_int64(0)
+    L = lib()
+    cnt = L.tworacle_bfs_level(n, _p(a, u64p), int(k), _p(f, u64p), len(f), ctypes.byref(ptr),
+                               ctypes.byref(gen), ctypes.byref(cand), threads)
+    if cnt < 0:
+        raise RuntimeError("oracle bfs_level failed (out of memory?)")
+    try:
+        out = np.ctypeslib.as_array(ptr, shape=(cnt,)).copy() if cnt else np.zeros(0, dtype=np.uint64)
+    finally:
+        L.tworacle_free(ptr)
+    return out, gen.value, cand.value
 
 
 def decide(rows, k: int, keep_levels: bool = True, threads: int = 0, on_level=None):

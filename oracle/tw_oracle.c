@@ -284,12 +284,13 @@ static void radix_sort(uint64_t *a, uint64_t *tmp, int64_t cnt)
 
 /* O4, one level of Listing 1 (§3.1) for the bound k: every S of in[] is
  * extended by every v outside S with |Q(S,v)| <= k; the successors are sorted
- * and duplicates removed.  out[] receives the distinct successors in ascending
- * order.  Returns their number, -1 on a bad argument or -2 if out_cap is too
- * small.  *generated (nullable) receives the number of feasible (S,v) pairs,
- * *candidates (nullable) the number of (S,v) pairs tried. */
+ * and duplicates removed.  *out receives a malloc'd array (free it with
+ * tworacle_free) of the distinct successors in ascending order.  Returns their
+ * number, or -1 on a bad argument or allocation failure.  *generated
+ * (nullable) receives the number of feasible (S,v) pairs, *candidates
+ * (nullable) the number of (S,v) pairs tried. */
 int64_t tworacle_bfs_level(int n, const uint64_t *rows, int k, const uint64_t *in,
-                           int64_t in_count, uint64_t *out, int64_t out_cap,
+                           int64_t in_count, uint64_t **out,
                            int64_t *generated, int64_t *candidates, int nthreads)
 {
     adjlist g;
@@ -364,13 +365,9 @@ int64_t tworacle_bfs_level(int n, const uint64_t *rows, int k, const uint64_t *i
         for (int64_t t = 0; t < total; t++)
             if (t == 0 || all_keys[t] != all_keys[t - 1])
                 all_keys[u++] = all_keys[t];
-        if (u > out_cap) {
-            result = -2;
-        } else {
-            if (u)
-                memcpy(out, all_keys, (size_t)u * sizeof(uint64_t));
-            result = u;
-        }
+        *out = all_keys;
+        all_keys = NULL;
+        result = u;
         if (generated)
             *generated = total;
         if (candidates)
@@ -385,6 +382,11 @@ int64_t tworacle_bfs_level(int n, const uint64_t *rows, int k, const uint64_t *i
     free(capb);
     free(tried);
     return result;
+}
+
+void tworacle_free(void *p)
+{
+    free(p);
 }
 
 /* Number of feasible (S,v) pairs over a list of states, without storing them

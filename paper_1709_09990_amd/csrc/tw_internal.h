@@ -1,0 +1,44 @@
+// Declarations shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace twk {
+
+// Device-resident counters of one level launch (zeroed before it).
+struct LevelCounters {
+    unsigned long long out_count;   // distinct successors claimed so far
+    unsigned long long successors;  // feasible (S, v) pairs, duplicates included
+    unsigned int overflow;          // 1: output capacity or probe limit exceeded
+    unsigned int pad;
+};
+
+// Arguments of one expansion launch (level i -> level i+1).
+struct LevelArgs {
+    const void *in;         // level i keys (uint32 or uint64)
+    uint64_t in_count;
+    void *out;              // level i+1 keys, capacity out_cap
+    uint8_t *out_lastv;     // vertex that created each level i+1 key
+    uint64_t out_cap;
+    void *table;            // open-addressing table, table_mask+1 slots, all EMPTY on entry
+    uint64_t table_mask;
+    const uint64_t *adj;    // n adjacency rows (device)
+    int n;
+    int k;
+    LevelCounters *ctr;
+    uint32_t max_probe;     // probe-length backstop
+    int key_bytes;          // 4 (n <= 32) or 8
+};
+
+constexpr int kBlock = 256;          // 4 waves of 64
+constexpr int kWavesPerBlock = kBlock / 64;
+
+hipError_t launch_fill_empty(void *table, uint64_t bytes, hipStream_t s);
+hipError_t launch_expand(const LevelArgs &a, unsigned grid_blocks, hipStream_t s);
+hipError_t launch_find(const void *keys, uint64_t count, uint64_t target, int key_bytes,
+                       unsigned long long *result, hipStream_t s);
+hipError_t launch_zero_counters(LevelCounters *c, hipStream_t s);
+
+}  // namespace twk

@@ -1,0 +1,271 @@
+// gfx950 kernels of the level-synchronous treewidth search (§3.1, Listing 1)
+// with exact duplicate removal (§3.2 replaced by an exact hash table).
+//
+// One wavefront expands one state S at a time.  Lane j holds adjacency row j,
+// so one ballot over "lane j is in S and touches the current set" is one
+// breadth-first step inside G[S].  For each component K of G[S] a second
+// ballot gives N_out(K), the vertices outside S adjacent to K.  For v outside
+// S, Q(S,v) (§2) is N(v) minus S together with N_out(K) for every component K
+// that v touches, minus v itself; v is feasible iff |Q(S,v)| <= k.  Feasible
+// successors S + {v} are inserted into an open-addressing table by atomic
+// compare-and-swap; the lane that claims an empty slot owns the new state,
+// stages it in LDS and the wave appends its staged winners to the next level
+// with one atomic per batch (stream compaction).
+#include "tw_internal.h"
+
+namespace twk {
+namespace {
+
+constexpr int kStage = 512;  // winners a wave stages in LDS before appending
+
+__device__ __forceinline__ uint64_t read_lane64(uint64_t x, int lane)
+{
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p)
+{
+    return __builtin_amdgcn_ballot_w64(p);
+}
+
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Slot of a key: two multiply-xorshift rounds, low bits.
+__device__ __forceinline__ uint64_t slot_of(uint64_t key)
+{
+    uint64_t h = key * 0xD6E8FEB86659FD93ull;
+    h ^= h >> 32;
+    h *= 0xD6E8FEB86659FD93ull;
+    h ^= h >> 32;
+    return h;
+}
+
+template <typename K>
+__device__ __forceinline__ K cas(K *p, K expected, K desired);
+
+template <>
+__device__ __forceinline__ uint32_t cas<uint32_t>(uint32_t *p, uint32_t e, uint32_t d)
+{
+    return atomicCAS(p, e, d);
+}
+
+template <>
+__device__ __forceinline__ uint64_t cas<uint64_t>(uint64_t *p, uint64_t e, uint64_t d)
+{
+    return (uint64_t)atomicCAS((unsigned long long *)p, (unsigned long long)e,
+                               (unsigned long long)d);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
+{
+    __shared__ K stage_key[kWavesPerBlock][kStage];
+    __shared__ uint8_t stage_v[kWavesPerBlock][kStage];
+
+    const K EMPTY = (K)~(K)0;
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = (int)(threadIdx.x >> 6);
+    const K *in = (const K *)a.in;
+    K *out = (K *)a.out;
+    K *table = (K *)a.table;
+    const uint64_t lanebit = 1ull << lane;
+    const uint64_t Aj = lane < a.n ? a.adj[lane] : 0ull;
+
+    const uint64_t wave_id = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
+    const uint64_t n_waves = (uint64_t)gridDim.x * kWavesPerBlock;
+
+    uint32_t staged = 0;       // wave-uniform
+    uint64_t feasible = 0;     // wave-uniform count of feasible pairs
+
+    // Append the staged winners to the next level (one atomic per batch).
+    auto flush = [&]() {
+        if (staged == 0)
+            return;
+        wave_lds_sync();
+        uint64_t base = 0;
+        if (lane == 0)
+            base = atomicAdd(&a.ctr->out_count, (unsigned long long)staged);
+        base = read_lane64(base, 0);
+        if (base + staged > a.out_cap) {
+            if (lane == 0)
+                atomicOr(&a.ctr->overflow, 1u);
+        } else {
+            for (uint32_t t = (uint32_t)lane; t < staged; t += 64) {
+                out[base + t] = stage_key[wv][t];
+                a.out_lastv[base + t] = stage_v[wv][t];
+            }
+        }
+        wave_lds_sync();
+        staged = 0;
+    };
+
+    for (uint64_t chunk = wave_id * 64; chunk < a.in_count; chunk += n_waves * 64) {
+        unsigned int ovf = __hip_atomic_load(&a.ctr->overflow, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        if (__builtin_amdgcn_readfirstlane(ovf))
+            break;
+        const uint64_t idx = chunk + (uint64_t)lane;
+        const uint64_t mine = idx < a.in_count ? (uint64_t)in[idx] : 0ull;
+        const uint64_t left = a.in_count - chunk;
+        const int cnt = left < 64 ? (int)left : 64;
+
+        for (int s = 0; s < cnt; ++s) {
+            const uint64_t S = read_lane64(mine, s);
+            const bool inS = (S >> lane) & 1ull;
+
+            // Components of G[S]; qacc collects N_out(K) of every K this lane touches.
+            uint64_t qacc = 0;
+            uint64_t rem = S;
+            while (rem) {
+                uint64_t comp = rem & (~rem + 1ull);
+                for (;;) {
+                    const uint64_t nxt = comp | ballot(inS && (Aj & comp) != 0ull);
+                    if (nxt == comp)
+                        break;
+                    comp = nxt;
+                }
+                rem &= ~comp;
+                const uint64_t nout = ballot(!inS && (Aj & comp) != 0ull);
+                if (nout & lanebit)
+                    qacc |= nout;
+            }
+            const uint64_t Q = (Aj | qacc) & ~S & ~lanebit;
+            const bool feas = lane < a.n && !inS && __popcll(Q) <= a.k;
+            const uint64_t feas_mask = ballot(feas);
+            feasible += (uint64_t)__popcll(feas_mask);
+            if (feas_mask == 0ull)
+                continue;
+
+            bool won = false;
+            const K key = (K)(S | lanebit);
+            if (feas) {
+                uint64_t h = slot_of((uint64_t)key) & a.table_mask;
+                for (uint32_t p = 0;; ++p) {
+                    const K old = cas<K>(&table[h], EMPTY, key);
+                    if (old == EMPTY) {
+                        won = true;
+                        break;
+                    }
+                    if (old == key)
+                        break;
+                    if (p >= a.max_probe) {
+                        atomicOr(&a.ctr->overflow, 1u);
+                        break;
+                    }
+                    h = (h + 1) & a.table_mask;
+                }
+            }
+            const uint64_t winners = ballot(won);
+            const uint32_t nw = (uint32_t)__popcll(winners);
+            if (nw == 0)
+                continue;
+            if (staged + nw > (uint32_t)kStage)
+                flush();
+            if (won) {
+                const uint32_t pos = staged + (uint32_t)lanes_below(winners);
+                stage_key[wv][pos] = key;
+                stage_v[wv][pos] = (uint8_t)lane;
+            }
+            staged += nw;
+        }
+    }
+    flush();
+    if (lane == 0 && feasible)
+        atomicAdd(&a.ctr->successors, (unsigned long long)feasible);
+}
+
+__global__ void fill_empty_kernel(uint4 *p, uint64_t n16)
+{
+    const uint4 v = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void zero_counters_kernel(LevelCounters *c)
+{
+    if (threadIdx.x == 0) {
+        c->out_count = 0;
+        c->successors = 0;
+        c->overflow = 0;
+        c->pad = 0;
+    }
+}
+
+template <typename K>
+__global__ void find_kernel(const K *keys, uint64_t count, K target, unsigned long long *result)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        if (keys[i] == target)
+            atomicMin(result, (unsigned long long)i);
+}
+
+unsigned blocks_for(uint64_t items, unsigned per_block, unsigned cap)
+{
+    uint64_t b = (items + per_block - 1) / per_block;
+    if (b < 1)
+        b = 1;
+    if (b > cap)
+        b = cap;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_fill_empty(void *table, uint64_t bytes, hipStream_t s)
+{
+    const uint64_t n16 = bytes / 16;
+    if (n16 == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(fill_empty_kernel, dim3(blocks_for(n16, 256, 8192)), dim3(256), 0, s,
+                       (uint4 *)table, n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_counters(LevelCounters *c, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand(const LevelArgs &a, unsigned grid_blocks, hipStream_t s)
+{
+    if (a.in_count == 0)
+        return hipSuccess;
+    if (a.key_bytes == 4)
+        hipLaunchKernelGGL(expand_kernel<uint32_t>, dim3(grid_blocks), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(expand_kernel<uint64_t>, dim3(grid_blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_find(const void *keys, uint64_t count, uint64_t target, int key_bytes,
+                       unsigned long long *result, hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    const unsigned g = blocks_for(count, 256, 4096);
+    if (key_bytes == 4)
+        hipLaunchKernelGGL(find_kernel<uint32_t>, dim3(g), dim3(256), 0, s, (const uint32_t *)keys,
+                           count, (uint32_t)target, result);
+    else
+        hipLaunchKernelGGL(find_kernel<uint64_t>, dim3(g), dim3(256), 0, s, (const uint64_t *)keys,
+                           count, target, result);
+    return hipGetLastError();
+}
+
+}  // namespace twk

@@ -1,0 +1,854 @@
+// Host runtime of libtw: the C-ABI of include/tw.h.
+//
+// decide(k) runs the level loop of Listing 1 (§3.1) on the device: level 0 is
+// {empty set}; each level is one expansion launch into an exact hash table and
+// a compacted next level.  The next level's size is unknown before the launch,
+// so it is estimated from the growth of the previous level; if the launch
+// overflows its output capacity (or the table's probe backstop), the level is
+// replayed with larger buffers — an exact answer is never traded for memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tw.h"
+#include "tw_internal.h"
+
+namespace {
+
+using twk::LevelCounters;
+
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Level {
+    Buf keys;
+    Buf lastv;
+    uint64_t count = 0;
+};
+
+struct Graph {
+    int n = 0;
+    uint64_t rows[64] = {};
+};
+
+}  // namespace
+
+struct tw_ctx {
+    tw_options opt{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int cu_count = 256;
+    std::string err;
+    std::vector<Buf> cache;  // free device buffers kept for reuse
+    Buf d_adj, d_ctr, d_find;
+    Buf table;               // current hash table (reused between levels)
+    LevelCounters *h_ctr = nullptr;      // pinned host mirror
+    unsigned long long *h_find = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+tw_status fail(tw_ctx *c, tw_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    return s;
+}
+
+#define HIP_TRY(c, expr)                                                                    \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((c), e_ == hipErrorOutOfMemory ? TW_ENOMEM : TW_EDEVICE, "%s: %s", \
+                        #expr, hipGetErrorString(e_));                                      \
+    } while (0)
+
+int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+uint64_t binom_sat(int n, int r)
+{
+    if (r < 0 || r > n)
+        return 0;
+    r = std::min(r, n - r);
+    unsigned __int128 v = 1;
+    for (int t = 1; t <= r; ++t) {
+        v = v * (unsigned)(n - r + t) / (unsigned)t;
+        if (v > (unsigned __int128)UINT64_MAX)
+            return UINT64_MAX;
+    }
+    return (uint64_t)v;
+}
+
+uint64_t pow2_at_least(uint64_t x)
+{
+    uint64_t p = 64;
+    while (p < x)
+        p <<= 1;
+    return p;
+}
+
+tw_status validate(tw_ctx *c, const tw_graph *g, Graph &out)
+{
+    if (!g || !g->adj)
+        return fail(c, TW_EINVAL, "graph or adjacency pointer is NULL");
+    if (g->n < 1 || g->n > 64)
+        return fail(c, TW_EINVAL, "n=%u outside 1..64", g->n);
+    out.n = (int)g->n;
+    const uint64_t all = out.n == 64 ? ~0ull : ((1ull << out.n) - 1);
+    for (int i = 0; i < out.n; ++i) {
+        uint64_t r = g->adj[i];
+        if (r & ~all)
+            return fail(c, TW_EINVAL, "row %d has bits at positions >= n", i);
+        if ((r >> i) & 1ull)
+            return fail(c, TW_EINVAL, "self-loop at vertex %d", i);
+        out.rows[i] = r;
+    }
+    for (int i = 0; i < out.n; ++i)
+        for (int j = 0; j < out.n; ++j)
+            if (((out.rows[i] >> j) & 1ull) != ((out.rows[j] >> i) & 1ull))
+                return fail(c, TW_EINVAL, "adjacency not symmetric at (%d,%d)", i, j);
+    return TW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device memory: a small cache of freed buffers, best fit, then hipMalloc
+// ---------------------------------------------------------------------------
+
+void release(tw_ctx *c, Buf &b)
+{
+    if (b.p)
+        c->cache.push_back(b);
+    b = Buf{};
+}
+
+void drop_cache(tw_ctx *c)
+{
+    for (Buf &b : c->cache)
+        (void)hipFree(b.p);
+    c->cache.clear();
+}
+
+tw_status acquire(tw_ctx *c, Buf &b, size_t bytes)
+{
+    if (b.p && b.bytes >= bytes)
+        return TW_OK;
+    release(c, b);
+    bytes = std::max<size_t>(bytes, 256);
+    int best = -1;
+    for (size_t t = 0; t < c->cache.size(); ++t)
+        if (c->cache[t].bytes >= bytes &&
+            (best < 0 || c->cache[t].bytes < c->cache[(size_t)best].bytes))
+            best = (int)t;
+    // reuse only if not grossly oversized
+    if (best >= 0 && c->cache[(size_t)best].bytes <= 4 * bytes + (1u << 20)) {
+        b = c->cache[(size_t)best];
+        c->cache.erase(c->cache.begin() + best);
+        return TW_OK;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(c->stream);
+        drop_cache(c);
+        e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, TW_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes,
+                        hipGetErrorString(e));
+        }
+    }
+    b.p = p;
+    b.bytes = bytes;
+    return TW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// host algorithms: minor-min-width (§3.3) and fill-in width (§2)
+// ---------------------------------------------------------------------------
+
+int mmw_bound(const Graph &g)
+{
+    uint64_t nb[64];
+    uint64_t alive = g.n == 64 ? ~0ull : ((1ull << g.n) - 1);
+    for (int v = 0; v < g.n; ++v)
+        nb[v] = g.rows[v];
+    int lb = 0;
+    while (popc(alive) >= 2) {
+        int d1 = 1 << 20, d2 = 1 << 20, v = -1;
+        for (uint64_t a = alive; a; a &= a - 1) {
+            const int x = __builtin_ctzll(a);
+            const int d = popc(nb[x]);
+            if (d < d1) {
+                d2 = d1;
+                d1 = d;
+                v = x;
+            } else if (d < d2) {
+                d2 = d;
+            }
+        }
+        lb = std::max(lb, d2);
+        if (d1 == 0) {
+            alive &= ~(1ull << v);
+            continue;
+        }
+        int u = -1, du = 1 << 20;
+        for (uint64_t a = nb[v]; a; a &= a - 1) {
+            const int x = __builtin_ctzll(a);
+            const int d = popc(nb[x]);
+            if (d < du) {
+                du = d;
+                u = x;
+            }
+        }
+        // contract v into u
+        for (uint64_t a = nb[v]; a; a &= a - 1) {
+            const int w = __builtin_ctzll(a);
+            nb[w] &= ~(1ull << v);
+            if (w != u) {
+                nb[w] |= 1ull << u;
+                nb[u] |= 1ull << w;
+            }
+        }
+        nb[v] = 0;
+        alive &= ~(1ull << v);
+    }
+    return lb;
+}
+
+int fill_in_width(const Graph &g, const int32_t *order)
+{
+    uint64_t adj[64];
+    uint64_t seen = 0;
+    for (int v = 0; v < g.n; ++v)
+        adj[v] = g.rows[v];
+    for (int t = 0; t < g.n; ++t) {
+        const int v = order[t];
+        if (v < 0 || v >= g.n || ((seen >> v) & 1ull))
+            return -1;
+        seen |= 1ull << v;
+    }
+    uint64_t alive = seen;
+    int width = 0;
+    for (int t = 0; t < g.n; ++t) {
+        const int v = order[t];
+        const uint64_t N = adj[v] & alive & ~(1ull << v);
+        width = std::max(width, popc(N));
+        for (uint64_t a = N; a; a &= a - 1) {
+            const int u = __builtin_ctzll(a);
+            adj[u] |= N & ~(1ull << u);
+        }
+        alive &= ~(1ull << v);
+    }
+    return width;
+}
+
+// ---------------------------------------------------------------------------
+// the level loop
+// ---------------------------------------------------------------------------
+
+struct RunStats {
+    uint64_t states_expanded = 0, expansions = 0, successors = 0, unique = 0, peak = 0;
+    uint32_t decisions = 0, levels = 0, retries = 0, launches = 0;
+    double kernel_seconds = 0;
+};
+
+void add_stats(tw_stats *st, const RunStats &r, double secs)
+{
+    if (!st)
+        return;
+    st->states_expanded = r.states_expanded;
+    st->expansions = r.expansions;
+    st->successors = r.successors;
+    st->unique = r.unique;
+    st->peak_frontier = r.peak;
+    st->decisions = r.decisions;
+    st->levels = r.levels;
+    st->retries = r.retries;
+    st->launches = r.launches;
+    st->seconds = secs;
+    st->kernel_seconds = r.kernel_seconds;
+}
+
+struct Sink {
+    void (*fn)(const tw_level_record *, void *) = nullptr;
+    void *user = nullptr;
+};
+
+tw_status emit_level(tw_ctx *c, const Sink &sink, int k, int i, const Level &lv, int key_bytes,
+                     uint64_t expansions, uint64_t successors)
+{
+    std::vector<uint64_t> keys(lv.count);
+    std::vector<uint8_t> lastv(lv.count, 0);
+    if (lv.count) {
+        if (key_bytes == 4) {
+            std::vector<uint32_t> k32(lv.count);
+            HIP_TRY(c, hipMemcpyAsync(k32.data(), lv.keys.p, lv.count * 4, hipMemcpyDeviceToHost,
+                                      c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            for (uint64_t t = 0; t < lv.count; ++t)
+                keys[t] = k32[t];
+        } else {
+            HIP_TRY(c, hipMemcpyAsync(keys.data(), lv.keys.p, lv.count * 8, hipMemcpyDeviceToHost,
+                                      c->stream));
+        }
+        if (i > 0)
+            HIP_TRY(c, hipMemcpyAsync(lastv.data(), lv.lastv.p, lv.count, hipMemcpyDeviceToHost,
+                                      c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    tw_level_record rec{};
+    rec.k = k;
+    rec.level = i;
+    rec.count = lv.count;
+    rec.expansions = expansions;
+    rec.successors = successors;
+    rec.states = keys.data();
+    rec.last_v = lastv.data();
+    sink.fn(&rec, sink.user);
+    return TW_OK;
+}
+
+// Runs decide(k).  With keep_levels, levels[0..L] stay on the device (each
+// trimmed to its exact size) for order reconstruction; otherwise only the
+// current pair is held.
+tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const Sink *sink,
+                     std::vector<Level> &levels, int *yes, RunStats &rs)
+{
+    const int n = g.n;
+    const int L = std::max(0, n - k - 1);
+    const int kb = n <= 32 ? 4 : 8;
+    rs.decisions++;
+
+    for (Level &lv : levels) {
+        release(c, lv.keys);
+        release(c, lv.lastv);
+    }
+    levels.assign(1, Level{});
+    // level 0 = {empty set}
+    {
+        Level &l0 = levels[0];
+        tw_status s = acquire(c, l0.keys, 8);
+        if (s != TW_OK)
+            return s;
+        HIP_TRY(c, hipMemsetAsync(l0.keys.p, 0, 8, c->stream));
+        l0.count = 1;
+    }
+    if (sink && sink->fn) {
+        tw_status s = emit_level(c, *sink, k, 0, levels[0], kb, 0, 0);
+        if (s != TW_OK)
+            return s;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_adj.p, g.rows, sizeof(uint64_t) * 64, hipMemcpyHostToDevice,
+                              c->stream));
+
+    const float alpha = (c->opt.load_factor > 0.f && c->opt.load_factor <= 0.9f)
+                            ? c->opt.load_factor
+                            : 0.5f;
+    double growth = (double)n;  // |level 1| <= n
+    Buf scratch_keys, scratch_lastv;
+    tw_status status = TW_OK;
+    uint64_t cur = 1;
+    int i = 0;
+
+    for (; i < L; ++i) {
+        Level &in = levels.back();
+        const uint64_t in_count = in.count;
+        const uint64_t bound = std::min<uint64_t>(binom_sat(n, i + 1),
+                                                  in_count > UINT64_MAX / 64
+                                                      ? UINT64_MAX
+                                                      : in_count * (uint64_t)(n - i));
+        uint64_t guess;
+        if (c->opt.capacity_override)
+            guess = c->opt.capacity_override;
+        else
+            guess = (uint64_t)std::min<double>((double)in_count * std::max(1.0, growth) * 2.0 + 1024.0,
+                                               1.8e19);
+        guess = std::min(guess, bound);
+        if (guess < 1)
+            guess = 1;
+
+        uint64_t out_count = 0, succ = 0;
+        for (;;) {
+            if (c->opt.max_states && guess > c->opt.max_states)
+                guess = std::max<uint64_t>(c->opt.max_states, 1);
+            uint64_t slots = pow2_at_least((uint64_t)((double)guess / alpha) + 1);
+            uint64_t out_cap = std::min<uint64_t>(bound, (uint64_t)((double)slots * 0.85));
+            if (out_cap < guess)
+                out_cap = guess;
+            if (c->opt.max_states)
+                out_cap = std::min<uint64_t>(out_cap, c->opt.max_states);
+            status = acquire(c, c->table, slots * kb);
+            if (status == TW_OK)
+                status = acquire(c, scratch_keys, out_cap * kb);
+            if (status == TW_OK)
+                status = acquire(c, scratch_lastv, out_cap);
+            if (status != TW_OK)
+                goto done;
+
+            HIP_TRY(c, twk::launch_fill_empty(c->table.p, slots * kb, c->stream));
+            HIP_TRY(c, twk::launch_zero_counters((LevelCounters *)c->d_ctr.p, c->stream));
+            twk::LevelArgs a{};
+            a.in = in.keys.p;
+            a.in_count = in_count;
+            a.out = scratch_keys.p;
+            a.out_lastv = (uint8_t *)scratch_lastv.p;
+            a.out_cap = out_cap;
+            a.table = c->table.p;
+            a.table_mask = slots - 1;
+            a.adj = (const uint64_t *)c->d_adj.p;
+            a.n = n;
+            a.k = k;
+            a.ctr = (LevelCounters *)c->d_ctr.p;
+            a.max_probe = (uint32_t)std::min<uint64_t>(slots, 1u << 16);
+            a.key_bytes = kb;
+            const uint64_t waves = (in_count + 63) / 64;
+            uint64_t blocks = (waves + twk::kWavesPerBlock - 1) / twk::kWavesPerBlock;
+            blocks = std::min<uint64_t>(std::max<uint64_t>(blocks, 1), (uint64_t)c->cu_count * 8);
+            if (c->opt.timing)
+                HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+            HIP_TRY(c, twk::launch_expand(a, (unsigned)blocks, c->stream));
+            if (c->opt.timing)
+                HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr.p, sizeof(LevelCounters),
+                                      hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            rs.launches++;
+            if (c->opt.timing) {
+                float ms = 0.f;
+                HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+                rs.kernel_seconds += ms * 1e-3;
+            }
+            const LevelCounters h = *c->h_ctr;
+            if (!h.overflow) {
+                out_count = h.out_count;
+                succ = h.successors;
+                break;
+            }
+            // overflow: regrow and replay the level
+            rs.retries++;
+            if (c->opt.max_states && out_cap >= c->opt.max_states) {
+                status = fail(c, TW_ECAPACITY, "level %d needs more than max_states=%llu states",
+                              i + 1, (unsigned long long)c->opt.max_states);
+                goto done;
+            }
+            if (out_cap >= bound && slots >= 2 * bound + 64) {
+                status = fail(c, TW_EDEVICE, "overflow at level %d with capacity at its bound", i + 1);
+                goto done;
+            }
+            guess = std::min<uint64_t>(bound, std::max<uint64_t>(guess * 4, h.out_count * 2));
+        }
+
+        rs.states_expanded += in_count;
+        rs.expansions += in_count * (uint64_t)(n - i);
+        rs.successors += succ;
+        rs.unique += out_count;
+        rs.levels++;
+        rs.peak = std::max(rs.peak, std::max(out_count, in_count));
+        growth = in_count ? (double)out_count / (double)in_count : 1.0;
+
+        // the new level: an exact-size copy when levels are kept, else the scratch pair itself
+        Level nl;
+        nl.count = out_count;
+        if (keep_levels || sink) {
+            status = acquire(c, nl.keys, std::max<uint64_t>(out_count, 1) * kb);
+            if (status == TW_OK)
+                status = acquire(c, nl.lastv, std::max<uint64_t>(out_count, 1));
+            if (status != TW_OK)
+                goto done;
+            if (out_count) {
+                HIP_TRY(c, hipMemcpyAsync(nl.keys.p, scratch_keys.p, out_count * kb,
+                                          hipMemcpyDeviceToDevice, c->stream));
+                HIP_TRY(c, hipMemcpyAsync(nl.lastv.p, scratch_lastv.p, out_count,
+                                          hipMemcpyDeviceToDevice, c->stream));
+            }
+        } else {
+            nl.keys = scratch_keys;
+            nl.lastv = scratch_lastv;
+            scratch_keys = Buf{};
+            scratch_lastv = Buf{};
+        }
+        if (sink && sink->fn) {
+            status = emit_level(c, *sink, k, i + 1, nl, kb, in_count * (uint64_t)(n - i), succ);
+            if (status != TW_OK) {
+                release(c, nl.keys);
+                release(c, nl.lastv);
+                goto done;
+            }
+        }
+        if (!keep_levels) {
+            Level &old = levels.back();
+            // the old input becomes the next scratch output
+            if (!sink) {
+                scratch_keys = old.keys;
+                scratch_lastv = old.lastv;
+                old.keys = Buf{};
+                old.lastv = Buf{};
+            } else {
+                release(c, old.keys);
+                release(c, old.lastv);
+            }
+            levels.back() = nl;
+        } else {
+            levels.push_back(nl);
+        }
+        cur = out_count;
+        if (out_count == 0)
+            break;
+    }
+done:
+    release(c, scratch_keys);
+    release(c, scratch_lastv);
+    if (status != TW_OK)
+        return status;
+    *yes = (i >= L && cur > 0) ? 1 : 0;
+    if (L == 0)
+        *yes = 1;
+    return TW_OK;
+}
+
+tw_status ensure_ctx_buffers(tw_ctx *c)
+{
+    tw_status s = acquire(c, c->d_adj, 64 * sizeof(uint64_t));
+    if (s == TW_OK)
+        s = acquire(c, c->d_ctr, sizeof(LevelCounters));
+    if (s == TW_OK)
+        s = acquire(c, c->d_find, sizeof(unsigned long long));
+    return s;
+}
+
+// Follow last_v back from a state of the last level to the empty set.
+tw_status reconstruct(tw_ctx *c, const Graph &g, int k, const std::vector<Level> &levels,
+                      int32_t *order)
+{
+    const int n = g.n;
+    const int L = (int)levels.size() - 1;
+    const int kb = n <= 32 ? 4 : 8;
+    std::vector<int> rev;
+    uint64_t S = 0;
+    uint64_t idx = 0;
+    if (L > 0) {
+        uint64_t key = 0;
+        HIP_TRY(c, hipMemcpyAsync(&key, levels[L].keys.p, kb, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        S = key;
+        const uint64_t SL = S;
+        for (int i = L; i >= 1; --i) {
+            uint8_t v = 0;
+            HIP_TRY(c, hipMemcpyAsync(&v, (const uint8_t *)levels[i].lastv.p + idx, 1,
+                                      hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            if (v >= n || !((S >> v) & 1ull))
+                return fail(c, TW_EDEVICE, "reconstruction: bad last vertex %d at level %d", v, i);
+            rev.push_back(v);
+            S &= ~(1ull << v);
+            if (i == 1)
+                break;
+            *c->h_find = ~0ull;
+            HIP_TRY(c, hipMemcpyAsync(c->d_find.p, c->h_find, 8, hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, twk::launch_find(levels[i - 1].keys.p, levels[i - 1].count, S, kb,
+                                        (unsigned long long *)c->d_find.p, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(c->h_find, c->d_find.p, 8, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            idx = *c->h_find;
+            if (idx == ~0ull)
+                return fail(c, TW_EDEVICE, "reconstruction: predecessor missing at level %d", i - 1);
+        }
+        S = SL;
+    }
+    int t = 0;
+    for (int r = (int)rev.size() - 1; r >= 0; --r)
+        order[t++] = rev[(size_t)r];
+    for (int v = 0; v < n; ++v)
+        if (!((S >> v) & 1ull))
+            order[t++] = v;
+    if (t != n)
+        return fail(c, TW_EDEVICE, "reconstruction produced %d of %d vertices", t, n);
+    const int w = fill_in_width(g, order);
+    if (w < 0 || w > k)
+        return fail(c, TW_EDEVICE, "reconstructed order has width %d > %d", w, k);
+    return TW_OK;
+}
+
+void free_levels(tw_ctx *c, std::vector<Level> &levels)
+{
+    for (Level &lv : levels) {
+        release(c, lv.keys);
+        release(c, lv.lastv);
+    }
+    levels.clear();
+}
+
+tw_status solve_one(tw_ctx *c, const Graph &g, int32_t *out_tw, int32_t *out_order, RunStats &rs)
+{
+    std::vector<Level> levels;
+    const int lb = mmw_bound(g);
+    for (int k = lb; k < g.n; ++k) {
+        int yes = 0;
+        tw_status s = run_decide(c, g, k, true, nullptr, levels, &yes, rs);
+        if (s != TW_OK) {
+            free_levels(c, levels);
+            return s;
+        }
+        if (yes) {
+            s = reconstruct(c, g, k, levels, out_order);
+            free_levels(c, levels);
+            if (s != TW_OK)
+                return s;
+            const int w = fill_in_width(g, out_order);
+            if (w != k)
+                return fail(c, TW_EDEVICE, "order width %d differs from treewidth %d", w, k);
+            *out_tw = k;
+            return TW_OK;
+        }
+    }
+    free_levels(c, levels);
+    return fail(c, TW_EDEVICE, "no bound k < n was accepted");
+}
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tw_status_str(tw_status s)
+{
+    switch (s) {
+    case TW_OK: return "ok";
+    case TW_EINVAL: return "invalid argument";
+    case TW_ENOMEM: return "out of memory";
+    case TW_EDEVICE: return "device error";
+    case TW_ECAPACITY: return "capacity limit reached";
+    }
+    return "unknown status";
+}
+
+const char *tw_last_error(const tw_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+tw_status tw_ctx_create(const tw_options *options, tw_ctx **out)
+{
+    if (!out)
+        return TW_EINVAL;
+    *out = nullptr;
+    tw_ctx *c = new (std::nothrow) tw_ctx();
+    if (!c)
+        return TW_ENOMEM;
+    if (options) {
+        size_t sz = options->struct_size ? std::min(options->struct_size, sizeof(tw_options))
+                                         : sizeof(tw_options);
+        std::memcpy(&c->opt, options, sz);
+    }
+    c->opt.struct_size = sizeof(tw_options);
+    if (c->opt.dedup != TW_DEDUP_EXACT) {
+        delete c;
+        return TW_EINVAL;
+    }
+    c->device = c->opt.device;
+    auto bad = [&](hipError_t e) {
+        (void)e;
+        delete c;
+        return TW_EDEVICE;
+    };
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess)
+        return bad(e);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->cu_count = prop.multiProcessorCount;
+    if (c->opt.stream) {
+        c->stream = (hipStream_t)c->opt.stream;
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            return bad(e);
+        c->own_stream = true;
+    }
+    if (hipHostMalloc((void **)&c->h_ctr, sizeof(LevelCounters), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_find, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+        tw_ctx_destroy(c);
+        return TW_ENOMEM;
+    }
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        tw_ctx_destroy(c);
+        return TW_EDEVICE;
+    }
+    if (ensure_ctx_buffers(c) != TW_OK) {
+        tw_ctx_destroy(c);
+        return TW_ENOMEM;
+    }
+    *out = c;
+    return TW_OK;
+}
+
+void tw_ctx_destroy(tw_ctx *c)
+{
+    if (!c)
+        return;
+    (void)hipSetDevice(c->device);
+    if (c->stream)
+        (void)hipStreamSynchronize(c->stream);
+    release(c, c->d_adj);
+    release(c, c->d_ctr);
+    release(c, c->d_find);
+    release(c, c->table);
+    drop_cache(c);
+    if (c->h_ctr)
+        (void)hipHostFree(c->h_ctr);
+    if (c->h_find)
+        (void)hipHostFree(c->h_find);
+    if (c->ev0)
+        (void)hipEventDestroy(c->ev0);
+    if (c->ev1)
+        (void)hipEventDestroy(c->ev1);
+    if (c->own_stream && c->stream)
+        (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+tw_status tw_decide(tw_ctx *c, const tw_graph *gr, int32_t k, int32_t *out_yes, tw_stats *stats)
+{
+    if (!c || !out_yes)
+        return TW_EINVAL;
+    c->err.clear();
+    Graph g;
+    tw_status s = validate(c, gr, g);
+    if (s != TW_OK)
+        return s;
+    if (k < 0)
+        return fail(c, TW_EINVAL, "k=%d < 0", k);
+    if (hipSetDevice(c->device) != hipSuccess)
+        return fail(c, TW_EDEVICE, "hipSetDevice failed");
+    const double t0 = now_s();
+    RunStats rs;
+    std::vector<Level> levels;
+    int yes = 0;
+    s = run_decide(c, g, k, false, nullptr, levels, &yes, rs);
+    free_levels(c, levels);
+    if (s != TW_OK)
+        return s;
+    *out_yes = yes;
+    add_stats(stats, rs, now_s() - t0);
+    return TW_OK;
+}
+
+tw_status tw_trace_decide(tw_ctx *c, const tw_graph *gr, int32_t k,
+                          void (*sink)(const tw_level_record *, void *), void *user, int32_t *out_yes)
+{
+    if (!c || !sink)
+        return TW_EINVAL;
+    c->err.clear();
+    Graph g;
+    tw_status s = validate(c, gr, g);
+    if (s != TW_OK)
+        return s;
+    if (k < 0)
+        return fail(c, TW_EINVAL, "k=%d < 0", k);
+    if (hipSetDevice(c->device) != hipSuccess)
+        return fail(c, TW_EDEVICE, "hipSetDevice failed");
+    RunStats rs;
+    std::vector<Level> levels;
+    Sink sk;
+    sk.fn = sink;
+    sk.user = user;
+    int yes = 0;
+    s = run_decide(c, g, k, false, &sk, levels, &yes, rs);
+    free_levels(c, levels);
+    if (s != TW_OK)
+        return s;
+    if (out_yes)
+        *out_yes = yes;
+    return TW_OK;
+}
+
+tw_status tw_solve(tw_ctx *c, const tw_graph *gr, int32_t *out_tw, int32_t *out_order, tw_stats *stats)
+{
+    if (!c || !out_tw || !out_order)
+        return TW_EINVAL;
+    c->err.clear();
+    Graph g;
+    tw_status s = validate(c, gr, g);
+    if (s != TW_OK)
+        return s;
+    if (hipSetDevice(c->device) != hipSuccess)
+        return fail(c, TW_EDEVICE, "hipSetDevice failed");
+    const double t0 = now_s();
+    RunStats rs;
+    s = solve_one(c, g, out_tw, out_order, rs);
+    if (s != TW_OK)
+        return s;
+    add_stats(stats, rs, now_s() - t0);
+    return TW_OK;
+}
+
+tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t *out_tw,
+                         int32_t *out_orders, tw_status *out_status, tw_stats *stats)
+{
+    if (!c || (count && (!gs || !out_tw || !out_orders || !out_status)))
+        return TW_EINVAL;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess)
+        return fail(c, TW_EDEVICE, "hipSetDevice failed");
+    const double t0 = now_s();
+    RunStats rs;
+    size_t off = 0;
+    for (uint32_t t = 0; t < count; ++t) {
+        Graph g;
+        tw_status s = validate(c, &gs[t], g);
+        if (s == TW_OK)
+            s = solve_one(c, g, &out_tw[t], out_orders + off, rs);
+        out_status[t] = s;
+        if (s != TW_OK)
+            out_tw[t] = -1;
+        off += gs[t].n;
+        if (s == TW_EDEVICE)
+            return s;
+    }
+    add_stats(stats, rs, now_s() - t0);
+    return TW_OK;
+}
+
+tw_status tw_mmw(const tw_graph *gr, int32_t *out_lb)
+{
+    if (!out_lb)
+        return TW_EINVAL;
+    Graph g;
+    tw_status s = validate(nullptr, gr, g);
+    if (s != TW_OK)
+        return s;
+    *out_lb = mmw_bound(g);
+    return TW_OK;
+}
+
+tw_status tw_order_width(const tw_graph *gr, const int32_t *order, int32_t *out_width)
+{
+    if (!order || !out_width)
+        return TW_EINVAL;
+    Graph g;
+    tw_status s = validate(nullptr, gr, g);
+    if (s != TW_OK)
+        return s;
+    *out_width = fill_in_width(g, order);
+    return TW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,259 @@
+"""ctypes binding of libtw.so (include/tw.h): argument marshalling only.
+
+Every step of the search runs in the HIP library; this module converts numpy
+arrays to pointers and status codes to exceptions.  If the library has not
+been built, every call raises — there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtw.so")
+
+TW_OK, TW_EINVAL, TW_ENOMEM, TW_EDEVICE, TW_ECAPACITY = range(5)
+TW_DEDUP_EXACT, TW_DEDUP_BLOOM = 0, 1
+TW_K_ASCENDING, TW_K_LEARNED = 0, 1
+
+
+class TwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"tw status {status}: {msg}")
+        self.status = status
+
+
+class _Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("adj", ctypes.POINTER(ctypes.c_uint64))]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_size_t),
+        ("device", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("dedup", ctypes.c_int),
+        ("load_factor", ctypes.c_float),
+        ("k_policy", ctypes.c_int),
+        ("weights_path", ctypes.c_char_p),
+        ("max_states", ctypes.c_uint64),
+        ("capacity_override", ctypes.c_uint64),
+        ("timing", ctypes.c_int),
+    ]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("states_expanded", ctypes.c_uint64),
+        ("expansions", ctypes.c_uint64),
+        ("successors", ctypes.c_uint64),
+        ("unique", ctypes.c_uint64),
+        ("peak_frontier", ctypes.c_uint64),
+        ("decisions", ctypes.c_uint32),
+        ("levels", ctypes.c_uint32),
+        ("retries", ctypes.c_uint32),
+        ("launches", ctypes.c_uint32),
+        ("seconds", ctypes.c_double),
+        ("kernel_seconds", ctypes.c_double),
+    ]
+
+
+class _LevelRecord(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int32),
+        ("level", ctypes.c_int32),
+        ("count", ctypes.c_uint64),
+        ("expansions", ctypes.c_uint64),
+        ("successors", ctypes.c_uint64),
+        ("states", ctypes.POINTER(ctypes.c_uint64)),
+        ("last_v", ctypes.POINTER(ctypes.c_uint8)),
+    ]
+
+
+_SINK = ctypes.CFUNCTYPE(None, ctypes.POINTER(_LevelRecord), ctypes.c_void_p)
+
+# every function declared in include/tw.h
+EXPORTS = (
+    "tw_ctx_create", "tw_ctx_destroy", "tw_decide", "tw_solve", "tw_solve_batch",
+    "tw_trace_decide", "tw_mmw", "tw_order_width", "tw_status_str", "tw_last_error",
+)
+
+_lib = None
+
+
+def load():
+    """Load libtw.so; raises if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "(python -m paper_1709_09990_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    L.tw_ctx_create.argtypes = [P(_Options), P(ctypes.c_void_p)]
+    L.tw_ctx_destroy.argtypes = [ctypes.c_void_p]
+    L.tw_ctx_destroy.restype = None
+    L.tw_decide.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_int32, P(ctypes.c_int32), P(_Stats)]
+    L.tw_solve.argtypes = [ctypes.c_void_p, P(_Graph), P(ctypes.c_int32), P(ctypes.c_int32), P(_Stats)]
+    L.tw_solve_batch.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_uint32, P(ctypes.c_int32),
+                                 P(ctypes.c_int32), P(ctypes.c_int), P(_Stats)]
+    L.tw_trace_decide.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_int32, _SINK, ctypes.c_void_p,
+                                  P(ctypes.c_int32)]
+    L.tw_mmw.argtypes = [P(_Graph), P(ctypes.c_int32)]
+    L.tw_order_width.argtypes = [P(_Graph), P(ctypes.c_int32), P(ctypes.c_int32)]
+    L.tw_status_str.argtypes = [ctypes.c_int]
+    L.tw_status_str.restype = ctypes.c_char_p
+    L.tw_last_error.argtypes = [ctypes.c_void_p]
+    L.tw_last_error.restype = ctypes.c_char_p
+    for name in ("tw_ctx_create", "tw_decide", "tw_solve", "tw_solve_batch", "tw_trace_decide",
+                 "tw_mmw", "tw_order_width"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _graph(rows):
+    a = np.ascontiguousarray(np.asarray(rows, dtype=np.uint64))
+    g = _Graph(len(a), a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    return g, a
+
+
+def _stats_dict(s: _Stats) -> dict:
+    return {name: getattr(s, name) for name, _ in _Stats._fields_}
+
+
+def mmw(rows) -> int:
+    L = load()
+    g, keep = _graph(rows)
+    out = ctypes.c_int32(0)
+    st = L.tw_mmw(ctypes.byref(g), ctypes.byref(out))
+    if st != TW_OK:
+        raise TwError(st, L.tw_status_str(st).decode())
+    return out.value
+
+
+def order_width(rows, order) -> int:
+    L = load()
+    g, keep = _graph(rows)
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    out = ctypes.c_int32(0)
+    st = L.tw_order_width(ctypes.byref(g), o.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                          ctypes.byref(out))
+    if st != TW_OK:
+        raise TwError(st, L.tw_status_str(st).decode())
+    return out.value
+
+
+@dataclass
+class Level:
+    k: int
+    level: int
+    count: int
+    expansions: int
+    successors: int
+    states: np.ndarray
+    last_v: np.ndarray
+
+
+class Context:
+    """A device context (one host thread at a time)."""
+
+    def __init__(self, device: int = 0, stream=None, dedup: int = TW_DEDUP_EXACT,
+                 load_factor: float = 0.0, max_states: int = 0, capacity_override: int = 0,
+                 timing: bool = False, k_policy: int = TW_K_ASCENDING, weights_path: str | None = None):
+        L = load()
+        self._L = L
+        o = _Options()
+        o.struct_size = ctypes.sizeof(_Options)
+        o.device = device
+        o.stream = ctypes.c_void_p(stream) if stream else None
+        o.dedup = dedup
+        o.load_factor = load_factor
+        o.k_policy = k_policy
+        self._wp = weights_path.encode() if weights_path else None
+        o.weights_path = self._wp
+        o.max_states = max_states
+        o.capacity_override = capacity_override
+        o.timing = 1 if timing else 0
+        h = ctypes.c_void_p()
+        st = L.tw_ctx_create(ctypes.byref(o), ctypes.byref(h))
+        if st != TW_OK:
+            raise TwError(st, "tw_ctx_create: " + L.tw_status_str(st).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.tw_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st: int):
+        if st != TW_OK:
+            msg = self._L.tw_last_error(self._h).decode()
+            raise TwError(st, msg or self._L.tw_status_str(st).decode())
+
+    def decide(self, rows, k: int):
+        g, keep = _graph(rows)
+        yes = ctypes.c_int32(0)
+        s = _Stats()
+        self._check(self._L.tw_decide(self._h, ctypes.byref(g), int(k), ctypes.byref(yes), ctypes.byref(s)))
+        return bool(yes.value), _stats_dict(s)
+
+    def solve(self, rows):
+        g, keep = _graph(rows)
+        tw = ctypes.c_int32(0)
+        order = np.zeros(len(keep), dtype=np.int32)
+        s = _Stats()
+        self._check(self._L.tw_solve(self._h, ctypes.byref(g), ctypes.byref(tw),
+                                     order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(s)))
+        return tw.value, order, _stats_dict(s)
+
+    def solve_batch(self, graphs):
+        arrs = [np.ascontiguousarray(np.asarray(r, dtype=np.uint64)) for r in graphs]
+        gs = (_Graph * max(1, len(arrs)))()
+        for t, a in enumerate(arrs):
+            gs[t].n = len(a)
+            gs[t].adj = a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        cnt = len(arrs)
+        tws = np.zeros(max(1, cnt), dtype=np.int32)
+        orders = np.zeros(max(1, sum(len(a) for a in arrs)), dtype=np.int32)
+        status = np.zeros(max(1, cnt), dtype=np.int32)
+        s = _Stats()
+        self._check(self._L.tw_solve_batch(
+            self._h, gs, cnt, tws.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(s)))
+        out_orders, off = [], 0
+        for a in arrs:
+            out_orders.append(orders[off:off + len(a)].copy())
+            off += len(a)
+        return tws[:cnt].copy(), out_orders, status[:cnt].copy(), _stats_dict(s)
+
+    def trace_decide(self, rows, k: int):
+        """decide(k) returning every level (states unordered) as Level records."""
+        g, keep = _graph(rows)
+        levels: list[Level] = []
+
+        def sink(rec_p, user):
+            r = rec_p.contents
+            c = int(r.count)
+            states = np.ctypeslib.as_array(r.states, shape=(c,)).copy() if c else np.zeros(0, np.uint64)
+            lastv = np.ctypeslib.as_array(r.last_v, shape=(c,)).copy() if c else np.zeros(0, np.uint8)
+            levels.append(Level(r.k, r.level, c, int(r.expansions), int(r.successors), states, lastv))
+
+        cb = _SINK(sink)
+        yes = ctypes.c_int32(0)
+        self._check(self._L.tw_trace_decide(self._h, ctypes.byref(g), int(k), cb, None, ctypes.byref(yes)))
+        return bool(yes.value), levels

@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports every function include/tw.h declares;
+host-only entry points (validation, minor-min-width, fill-in width) agree with
+the oracle.  No device call is made here."""
+import ctypes
+import os
+import random
+import re
+
+import numpy as np
+import pytest
+
+from paper_1709_09990_amd import graphs as G
+from paper_1709_09990_amd import tw as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "tw.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(tw_[a-z_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    names = _header_functions()
+    assert "tw_decide" in names and "tw_solve" in names and "tw_solve_batch" in names
+    assert set(names) == set(T.EXPORTS)
+    lib = ctypes.CDLL(T.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    L = T.load()
+    for s in range(5):
+        assert L.tw_status_str(s)
+
+
+def test_mmw_matches_oracle(oracle):
+    rng = random.Random(21)
+    for t in range(300):
+        n = rng.randint(1, 40)
+        rows = G.gnp(n, rng.uniform(0.05, 0.7), 7000 + t)
+        assert T.mmw(rows) == oracle.mmw(rows), t
+    for t in range(40):
+        rows = G.partial_ktree(20 + t, 4 + t % 6, 0.3, 7500 + t)
+        assert T.mmw(rows) == oracle.mmw(rows)
+    for rows in G.workload_single_n40().values():
+        assert T.mmw(rows) == oracle.mmw(rows)
+    assert T.mmw(G.complete(64)) == oracle.mmw(G.complete(64)) == 63
+
+
+def test_order_width_matches_oracle(oracle):
+    rng = random.Random(22)
+    for t in range(300):
+        n = rng.randint(1, 64)
+        rows = G.gnp(n, rng.uniform(0.02, 0.4), 8000 + t)
+        order = list(range(n))
+        rng.shuffle(order)
+        assert T.order_width(rows, order) == oracle.order_width(rows, order)
+    assert T.order_width(G.path(3), [0, 0, 1]) == -1
+
+
+@pytest.mark.parametrize("rows", [
+    np.array([0b10, 0b00], dtype=np.uint64),          # not symmetric
+    np.array([0b01], dtype=np.uint64),                # self-loop
+    np.array([0b100, 0b000], dtype=np.uint64),        # bit beyond n
+    np.zeros(0, dtype=np.uint64),                     # n = 0
+])
+def test_invalid_graphs_rejected_on_host(rows):
+    with pytest.raises(T.TwError) as e:
+        T.mmw(rows)
+    assert e.value.status == T.TW_EINVAL

@@ -1,0 +1,250 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Every level of every bound k is compared as a set (the device writes states
+in a nondeterministic order, so both sides are sorted): the same states, the
+same counts, the same numbers of candidate and feasible (S, v) pairs.  Each
+state's recorded last vertex must lead back into the previous level with a
+feasible degree.  Treewidth must equal O1's and the returned order must have
+exactly that width by the oracle's fill-in count.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1709_09990_amd import graphs as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1709_09990_amd import tw as T
+    c = T.Context(device=0)
+    yield c
+    c.close()
+
+
+def _check_levels(oracle, rows, k, levels_gpu, ref_levels, ref_stats=None):
+    n = len(rows)
+    assert len(levels_gpu) <= len(ref_levels)
+    for lv in levels_gpu:
+        i = lv.level
+        ref = ref_levels[i]
+        got = np.sort(lv.states)
+        assert lv.count == len(ref), (k, i, lv.count, len(ref))
+        assert np.array_equal(got, ref), (k, i)
+        assert len(np.unique(got)) == len(got)
+        if i > 0:
+            assert lv.expansions == len(ref_levels[i - 1]) * (n - i + 1)
+            if ref_stats is not None:
+                assert lv.successors == ref_stats[i - 1][1], (k, i)
+            # the recorded creator leads back into level i-1 with degree <= k
+            prev = ref_levels[i - 1]
+            sample = np.arange(len(got)) if len(got) <= 4000 else np.linspace(0, len(got) - 1, 4000).astype(int)
+            for t in sample:
+                S = int(lv.states[t])
+                v = int(lv.last_v[t])
+                assert (S >> v) & 1
+                P = S & ~(1 << v)
+                idx = np.searchsorted(prev, np.uint64(P))
+                assert idx < len(prev) and int(prev[idx]) == P
+                assert oracle.q_degree(rows, P, v) <= k
+    # levels stop early only after an empty one
+    if len(levels_gpu) < len(ref_levels):
+        assert levels_gpu[-1].count == 0
+
+
+def _parity_all_k(oracle, ctx, rows, k_values=None):
+    n = len(rows)
+    tw, table = oracle.subset_dp(rows)
+    if k_values is None:
+        k_values = range(max(0, oracle.mmw(rows) - 1), min(n, tw + 2))
+    for k in k_values:
+        ref_levels = oracle.frontiers_from_dp(rows, k, table)
+        yes, levels = ctx.trace_decide(rows, k)
+        assert yes == (k >= tw), (k, tw)
+        _check_levels(oracle, rows, k, levels, ref_levels)
+    return tw
+
+
+def test_small_graph_32bit_levels_match_dp(oracle, ctx):
+    """G(20, 0.3), seed 1001: every level for every k around tw equals O1."""
+    rows = G.workload_single_small(1001)
+    tw = _parity_all_k(oracle, ctx, rows)
+    got_tw, order, st = ctx.solve(rows)
+    assert got_tw == tw
+    assert oracle.order_width(rows, order) == tw
+    assert sorted(order.tolist()) == list(range(len(rows)))
+
+
+@pytest.mark.parametrize("seed", range(1002, 1033))
+def test_small_graph_seeds(oracle, ctx, seed):
+    rows = G.workload_single_small(seed)
+    tw, table = oracle.subset_dp(rows)
+    got_tw, order, st = ctx.solve(rows)
+    assert got_tw == tw
+    assert oracle.order_width(rows, order) == tw
+    # levels at tw and tw-1 against O1 with feasible-pair counts from O4
+    for k in (tw - 1, tw):
+        if k < 0:
+            continue
+        ref_levels = oracle.frontiers_from_dp(rows, k, table)
+        _, _, ref_stats = oracle.decide(rows, k)
+        yes, levels = ctx.trace_decide(rows, k)
+        assert yes == (k == tw)
+        _check_levels(oracle, rows, k, levels, ref_levels, ref_stats)
+
+
+@pytest.mark.parametrize("n,p,seed", [(8, 0.5, 1), (13, 0.4, 2), (17, 0.25, 3), (22, 0.2, 4),
+                                       (24, 0.15, 5), (28, 0.25, 6), (30, 0.3, 7), (32, 0.35, 8),
+                                       (32, 0.25, 9)])
+def test_random_graphs_32bit(oracle, ctx, n, p, seed):
+    """Sizes up to the 32-bit boundary; O4 supplies levels and pair counts."""
+    rows = G.gnp(n, p, 11000 + seed)
+    lb = oracle.mmw(rows)
+    tw = oracle.treewidth_bfs(rows, lb)
+    got_tw, order, _ = ctx.solve(rows)
+    assert got_tw == tw
+    assert oracle.order_width(rows, order) == tw
+    for k in (tw - 1, tw):
+        if k < 0:
+            continue
+        _, ref_levels, ref_stats = oracle.decide(rows, k)
+        _, levels = ctx.trace_decide(rows, k)
+        _check_levels(oracle, rows, k, levels, ref_levels, ref_stats)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: G.gnp(34, 0.3, 12001),
+    lambda: G.gnp(38, 0.35, 12002),
+    lambda: G.grid(3, 12),
+    lambda: G.complete_bipartite(20, 20),
+    lambda: G.gnp(44, 0.4, 12008),
+    lambda: G.gnp(56, 0.45, 12010),
+    lambda: G.gnp(64, 0.5, 12009),
+    lambda: G.complete_multipartite([8] * 8),
+    lambda: G.path(64),
+])
+def test_random_graphs_64bit(oracle, ctx, maker):
+    """n > 32 (64-bit keys); O4 supplies the levels."""
+    rows = maker()
+    lb = oracle.mmw(rows)
+    tw = oracle.treewidth_bfs(rows, lb)
+    got_tw, order, _ = ctx.solve(rows)
+    assert got_tw == tw
+    assert oracle.order_width(rows, order) == tw
+    for k in (tw - 1, tw):
+        if k < 0:
+            continue
+        _, ref_levels, ref_stats = oracle.decide(rows, k)
+        _, levels = ctx.trace_decide(rows, k)
+        _check_levels(oracle, rows, k, levels, ref_levels, ref_stats)
+
+
+def test_closed_form_sizes_edgeless(ctx):
+    """Edgeless n=24 at k=0: |F_i| = C(24, i) (2.7 M states at the peak), each
+    generated (i+1) times — the hash dedup against a closed form."""
+    n = 24
+    yes, levels = ctx.trace_decide(G.edgeless(n), 0)
+    assert yes and len(levels) == n
+    for lv in levels:
+        assert lv.count == math.comb(n, lv.level)
+        if lv.level > 0:
+            assert lv.successors == math.comb(n, lv.level - 1) * (n - lv.level + 1)
+        assert len(np.unique(lv.states)) == lv.count
+        assert np.all(np.bitwise_count(lv.states) == lv.level)
+
+
+def test_closed_form_counts_64bit(ctx):
+    """Every subset is feasible for the edgeless graph at any k and for
+    disjoint K_c at k >= c-1, so with L = n-k-1 levels the counts are binomial
+    sums.  Edgeless n=40 at k=31 reaches C(40, 8) = 77 M states."""
+    n, k = 40, 31
+    L = n - k - 1
+    yes, st = ctx.decide(G.edgeless(n), k)
+    assert yes
+    assert st["unique"] == sum(math.comb(n, i) for i in range(1, L + 1))
+    assert st["successors"] == sum(math.comb(n, i) * (n - i) for i in range(0, L))
+    assert st["expansions"] == st["successors"]
+    assert st["peak_frontier"] == math.comb(n, L)
+    rows = G.disjoint_cliques(4, 9)
+    n = len(rows)
+    yes, levels = ctx.trace_decide(rows, 29)
+    assert yes
+    for lv in levels:
+        assert lv.count == math.comb(n, lv.level)
+        assert len(np.unique(lv.states)) == lv.count
+    yes, st = ctx.decide(rows, 27)
+    assert yes and st["peak_frontier"] == math.comb(n, 8)
+    yes, levels = ctx.trace_decide(rows, 2)
+    assert not yes and levels[1].count == 0 and len(levels) == 2
+
+
+def test_path_closed_form_levels(ctx):
+    """Path on 64 vertices at k=1: the feasible sets of size i are a prefix
+    plus a suffix, i+1 of them."""
+    yes, levels = ctx.trace_decide(G.path(64), 1)
+    assert yes
+    for lv in levels:
+        assert lv.count == lv.level + 1
+
+
+@pytest.mark.parametrize("rows,tw", [
+    (G.complete(1), 0), (G.complete(2), 1), (G.edgeless(5), 0), (G.complete(12), 11),
+    (G.petersen(), 4), (G.complete_bipartite(3, 5), 3), (G.grid(4, 5), 4), (G.cycle(9), 2),
+    (G.complete(40), 39), (G.edgeless(20), 0), (G.path(64), 1),
+    (G.disjoint_cliques(5, 3), 4),
+])
+def test_edge_cases_and_closed_forms(oracle, ctx, rows, tw):
+    got, order, _ = ctx.solve(rows)
+    assert got == tw
+    assert oracle.order_width(rows, order) == tw
+    n = len(rows)
+    assert ctx.decide(rows, n - 1)[0]          # k >= n-1: YES with no level
+    if tw > 0:
+        assert not ctx.decide(rows, tw - 1)[0]
+
+
+def test_overflow_regrow_replay_is_exact(oracle, ctx):
+    """A tiny first guess forces overflow -> regrow -> replay at every level;
+    the levels must be identical and the retries counted."""
+    from paper_1709_09990_amd import tw as T
+    rows = G.workload_single_small(1001)
+    tw, table = oracle.subset_dp(rows)
+    with T.Context(device=0, capacity_override=1) as small:
+        yes, levels = small.trace_decide(rows, tw)
+        assert yes
+        _check_levels(oracle, rows, tw, levels, oracle.frontiers_from_dp(rows, tw, table))
+        _, st = small.decide(rows, tw)
+        assert st["retries"] > 0
+        got, order, _ = small.solve(rows)
+        assert got == tw and oracle.order_width(rows, order) == tw
+
+
+def test_capacity_limit_is_an_error(ctx):
+    from paper_1709_09990_amd import tw as T
+    with T.Context(device=0, max_states=100) as lim:
+        with pytest.raises(T.TwError) as e:
+            lim.decide(G.edgeless(20), 0)
+        assert e.value.status == T.TW_ECAPACITY
+
+
+def test_invalid_arguments(ctx):
+    from paper_1709_09990_amd import tw as T
+    with pytest.raises(T.TwError) as e:
+        ctx.decide(np.array([0b10, 0b00], dtype=np.uint64), 1)
+    assert e.value.status == T.TW_EINVAL
+    with pytest.raises(T.TwError) as e:
+        ctx.decide(G.path(4), -1)
+    assert e.value.status == T.TW_EINVAL
+
+
+def test_batch_equals_single(oracle, ctx):
+    graphs = G.workload_batch(24, seed0=31000, n_lo=8, n_hi=26)
+    tws, orders, status, st = ctx.solve_batch(graphs)
+    for rows, tw, order, s in zip(graphs, tws, orders, status):
+        assert s == 0
+        single, _, _ = ctx.solve(rows)
+        assert tw == single
+        assert oracle.order_width(rows, order) == tw
