@@ -81,6 +81,11 @@ typedef struct {
     uint64_t capacity_override; /* test hook: first guess of every level's size (0 = estimate); a
                                    small value forces the overflow -> regrow -> replay path */
     int timing;               /* 1: time every expansion launch with HIP events (tw_stats.kernel_*) */
+    /* tw_solve_batch: graphs with n <= 48 run in one persistent launch, each with
+       its own state arena (all levels of its current bound) and hash table. */
+    uint64_t batch_graph_states; /* arena states per graph (0 = 2^20); a graph that outgrows its
+                                    arena or table is re-solved alone by the tw_solve path */
+    uint32_t batch_chunk;     /* states per work-queue task, multiple of 64 (0 = 256) */
 } tw_options;
 
 /* Counters of one call (summed over every bound k and level it ran). */
@@ -118,6 +123,12 @@ tw_status tw_solve(tw_ctx *ctx, const tw_graph *g, int32_t *out_tw, int32_t *out
 
 /* tw_solve for count graphs of uneven size.  out_tw[count], out_status[count];
  * out_orders holds the orders back to back (sum of n entries, graph order).
+ * Graphs with n <= 48 are solved together in one persistent kernel: a device
+ * work queue of (graph, level) jobs cut into chunks, the last chunk of a level
+ * advancing that graph's level or bound on the device; the others (and any
+ * graph whose arena or table fills up) go through the tw_solve path.  The
+ * treewidths equal tw_solve's; each order is checked by fill-in to have
+ * exactly that width (several orders may qualify).
  * A graph that fails gets its own status; the others still complete.  The
  * return value is TW_OK unless an argument is invalid or the device failed. */
 tw_status tw_solve_batch(tw_ctx *ctx, const tw_graph *gs, uint32_t count, int32_t *out_tw,

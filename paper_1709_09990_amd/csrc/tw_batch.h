@@ -1,0 +1,80 @@
+// Device structures of the batched persistent search (many graphs, one launch).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace twk {
+
+// Graph status in a batch.
+enum : uint32_t {
+    kBatchRunning = 0,
+    kBatchDone = 1,      // YES at bound k; the levels of that run are in the arena
+    kBatchFallback = 2,  // arena or table too small: solve it alone on the host path
+};
+
+constexpr int kBatchKeyBits = 48;   // keys below bit 48, table tag above
+constexpr int kBatchMaxN = 48;
+
+// Per-graph state, device resident.  Written by the host before the launch;
+// afterwards only by the wave that finishes a level of this graph (counters
+// by atomics).
+struct BatchGraph {
+    uint64_t adj[64];
+    uint64_t *keys;          // arena: the levels of the current bound, back to back
+    uint8_t *lastv;
+    uint64_t arena_cap;      // states the arena holds
+    uint64_t *table;         // tagged open-addressing table (tag << 48 | key), zero-initialised
+    uint64_t table_mask;
+    uint64_t level_off[66];  // arena offset of level i (current bound)
+    unsigned long long out_count;   // states claimed for the level being built
+    unsigned long long successors;  // feasible pairs over the whole solve
+    unsigned long long expansions;  // (S, v) pairs over the whole solve
+    unsigned long long states;      // states expanded over the whole solve
+    unsigned long long peak;        // largest level
+    unsigned long long unique;      // states written over the whole solve
+    uint32_t overflow;
+    uint32_t status;
+    int32_t n, k, level, L;
+    int32_t tw;
+    uint32_t tag;
+    uint32_t decisions, levels_run;
+};
+
+// One level of one graph: nchunks tasks of up to chunk states.
+struct BatchJob {
+    int32_t graph;
+    int32_t level;
+    uint64_t begin;          // arena offset of the level's first state
+    uint64_t count;
+    uint32_t nchunks;
+    uint32_t cursor;         // next chunk to hand out (atomic)
+    uint32_t done;           // chunks finished (atomic)
+    uint32_t ready;          // 1 once the fields above are written (release/acquire)
+};
+
+struct BatchQueue {
+    unsigned long long head;      // first job not yet exhausted
+    unsigned long long tail;      // jobs reserved
+    unsigned long long capacity;
+    uint32_t active;              // graphs still running
+    uint32_t abort;               // set if a wait exceeded its bound or the job array filled
+};
+
+struct BatchArgs {
+    BatchGraph *graphs;
+    BatchJob *jobs;
+    BatchQueue *q;
+    uint32_t chunk;          // states per task (multiple of 64)
+    uint32_t max_probe;
+    float max_load;          // a level above this fraction of the table overflows
+    uint32_t spin_limit;     // sleeps a wave may spend waiting for work before aborting
+};
+
+hipError_t launch_batch(const BatchArgs &a, unsigned grid_blocks, hipStream_t s);
+hipError_t launch_batch_reconstruct(BatchGraph *graphs, const int32_t *ids, int count,
+                                    int32_t *orders /* count x 64 */, hipStream_t s);
+int batch_blocks_per_cu();
+
+}  // namespace twk

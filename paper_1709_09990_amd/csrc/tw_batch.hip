@@ -1,0 +1,354 @@
+// Batched persistent search: every graph of a batch runs its own ascending-k
+// level loop (§3.1, Listing 1) inside ONE launch.
+//
+// Work is a device queue of jobs, one job per (graph, level); a job is cut
+// into chunks of `chunk` states and every wave of the persistent grid takes
+// chunks from the job at the queue head.  The wave that finishes the last
+// chunk of a level advances that graph alone: next level, next bound k after a
+// NO (empty level), or done after a YES — so graphs of different sizes never
+// wait for each other.  Each graph has its own arena (all levels of its
+// current bound, back to back, for the order backtrack) and its own hash
+// table.  Table slots carry a 16-bit tag above the 48-bit state; a slot whose
+// tag is not the level's tag counts as empty, so tables are never cleared.
+//
+// Exit: every wave leaves once no graph is running, or after spin_limit
+// consecutive sleeps without work (abort flag; the host reports an error).
+#include "tw_batch.h"
+#include "tw_wave.h"
+
+namespace twk {
+namespace {
+
+constexpr int kBatchBlock = 256;
+constexpr int kBatchWaves = kBatchBlock / 64;
+constexpr int kBatchStage = 512;
+constexpr uint64_t kKeyMask = (1ull << kBatchKeyBits) - 1;
+
+template <typename T>
+__device__ __forceinline__ T ld_acquire(T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_relaxed(T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by one lane: append a job for (g, level).
+__device__ void push_job(const BatchArgs &a, int g, int level, uint64_t begin, uint64_t count)
+{
+    const unsigned long long idx = atomicAdd(&a.q->tail, 1ull);
+    if (idx >= a.q->capacity) {
+        atomicOr(&a.q->abort, 1u);
+        return;
+    }
+    BatchJob *j = &a.jobs[idx];
+    j->graph = g;
+    j->level = level;
+    j->begin = begin;
+    j->count = count;
+    j->nchunks = (uint32_t)((count + a.chunk - 1) / a.chunk);
+    j->cursor = 0;
+    j->done = 0;
+    __hip_atomic_store(&j->ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by one lane after every chunk of (g, level) has finished.
+__device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_count)
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    BatchGraph *G = &a.graphs[g];
+    const uint64_t cnt = ld_relaxed(&G->out_count);
+    const uint32_t ovf = ld_relaxed(&G->overflow);
+    G->states += in_count;
+    G->expansions += in_count * (uint64_t)(G->n - level);
+    G->levels_run++;
+    G->unique += cnt;
+    if (cnt > G->peak)
+        G->peak = cnt;
+    if (ovf || G->tag >= 0xFFFFu) {
+        G->status = kBatchFallback;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        atomicSub(&a.q->active, 1u);
+        return;
+    }
+    if (cnt == 0) {
+        // NO at bound k: restart at level 0 with k + 1
+        G->k++;
+        G->decisions++;
+        if (G->k >= G->n - 1) {
+            G->tw = G->k;
+            G->level = 0;
+            G->L = 0;
+            G->status = kBatchDone;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            atomicSub(&a.q->active, 1u);
+            return;
+        }
+        G->L = G->n - G->k - 1;
+        G->level = 0;
+        G->tag++;
+        G->out_count = 0;
+        G->level_off[0] = 0;
+        G->level_off[1] = 1;  // level 0 is the empty set (never read from the arena)
+        push_job(a, g, 0, 0, 1);
+        return;
+    }
+    const int next = level + 1;
+    G->level_off[next + 1] = G->level_off[next] + cnt;
+    if (next == G->L) {
+        // YES at bound k: the levels of this bound stay in the arena
+        G->tw = G->k;
+        G->level = next;
+        G->status = kBatchDone;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        atomicSub(&a.q->active, 1u);
+        return;
+    }
+    G->level = next;
+    G->tag++;
+    G->out_count = 0;
+    push_job(a, g, next, G->level_off[next], cnt);
+}
+
+__global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
+{
+    __shared__ uint64_t stage_key[kBatchWaves][kBatchStage];
+    __shared__ uint8_t stage_v[kBatchWaves][kBatchStage];
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = (int)(threadIdx.x >> 6);
+    uint32_t spins = 0;
+
+    for (;;) {
+        if (first_lane32(ld_relaxed(&a.q->abort)))
+            break;
+        if (first_lane32(ld_relaxed(&a.q->active)) == 0)
+            break;
+        const uint64_t h = read_lane64(ld_relaxed(&a.q->head), 0);
+        const uint64_t t = read_lane64(ld_relaxed(&a.q->tail), 0);
+        bool wait = h >= t || h >= a.q->capacity;
+        BatchJob *J = nullptr;
+        if (!wait) {
+            J = &a.jobs[h];
+            wait = first_lane32(ld_acquire(&J->ready)) == 0;
+        }
+        if (wait) {
+            if (++spins > a.spin_limit) {
+                if (lane == 0)
+                    atomicOr(&a.q->abort, 1u);
+                break;
+            }
+            // back off while the queue is empty (polls hit a few shared words)
+            if (spins < 64)
+                __builtin_amdgcn_s_sleep(2);
+            else
+                __builtin_amdgcn_s_sleep(32);
+            continue;
+        }
+        uint32_t c = 0;
+        if (lane == 0)
+            c = atomicAdd(&J->cursor, 1u);
+        c = (uint32_t)__builtin_amdgcn_readlane((int)c, 0);
+        const uint32_t nchunks = first_lane32(J->nchunks);
+        if (c >= nchunks) {
+            if (lane == 0)
+                atomicCAS(&a.q->head, (unsigned long long)h, (unsigned long long)(h + 1));
+            continue;
+        }
+        spins = 0;
+        const int g = (int)first_lane32((uint32_t)J->graph);
+        const int level = (int)first_lane32((uint32_t)J->level);
+        const uint64_t begin = read_lane64(J->begin, 0);
+        const uint64_t count = read_lane64(J->count, 0);
+        BatchGraph *G = &a.graphs[g];
+        const int n = (int)first_lane32((uint32_t)G->n);
+        const int k = (int)first_lane32((uint32_t)G->k);
+        const uint64_t tag = (uint64_t)first_lane32(G->tag) << kBatchKeyBits;
+        const uint64_t tmask = read_lane64(G->table_mask, 0);
+        const uint64_t out_base = read_lane64(G->level_off[level + 1], 0);
+        const uint64_t arena_cap = read_lane64(G->arena_cap, 0);
+        const uint64_t max_fill = (uint64_t)((double)(tmask + 1) * a.max_load);
+        uint64_t *keys = G->keys;
+        uint8_t *lastv = G->lastv;
+        uint64_t *table = G->table;
+        const uint64_t Aj = lane < n ? G->adj[lane] : 0ull;
+        const uint64_t lanebit = 1ull << lane;
+
+        uint32_t staged = 0;
+        uint64_t feasible = 0;
+        bool overflow = false;
+        auto flush = [&]() {
+            if (staged == 0)
+                return;
+            wave_lds_sync();
+            uint64_t base = 0;
+            if (lane == 0)
+                base = atomicAdd(&G->out_count, (unsigned long long)staged);
+            base = read_lane64(base, 0);
+            if (base + staged > max_fill || out_base + base + staged > arena_cap) {
+                overflow = true;
+            } else {
+                for (uint32_t q = (uint32_t)lane; q < staged; q += 64) {
+                    keys[out_base + base + q] = stage_key[wv][q];
+                    lastv[out_base + base + q] = stage_v[wv][q];
+                }
+            }
+            wave_lds_sync();
+            staged = 0;
+        };
+
+        const uint64_t lo = (uint64_t)c * a.chunk;
+        const uint64_t hi = lo + a.chunk < count ? lo + a.chunk : count;
+        for (uint64_t chunk = lo; chunk < hi && !overflow; chunk += 64) {
+            const uint64_t idx = chunk + (uint64_t)lane;
+            const uint64_t mine = (idx < hi && level > 0) ? keys[begin + idx] : 0ull;
+            const int cnt = hi - chunk < 64 ? (int)(hi - chunk) : 64;
+            for (int s = 0; s < cnt; ++s) {
+                const uint64_t S = read_lane64(mine, s);
+                const bool feas = lane_feasible(S, Aj, lane, n, k);
+                const uint64_t fmask = ballot(feas);
+                feasible += (uint64_t)__popcll(fmask);
+                if (fmask == 0)
+                    continue;
+                const uint64_t key = S | lanebit;
+                bool won = false;
+                if (feas) {
+                    const uint64_t want = tag | key;
+                    uint64_t slot = slot_hash(key) & tmask;
+                    uint64_t cur = ld_relaxed(&table[slot]);
+                    for (uint32_t p = 0;;) {
+                        if ((cur & ~kKeyMask) == tag) {
+                            if (cur == want)
+                                break;  // already claimed this level
+                            if (++p > a.max_probe) {
+                                overflow = true;
+                                break;
+                            }
+                            slot = (slot + 1) & tmask;
+                            cur = ld_relaxed(&table[slot]);
+                            continue;
+                        }
+                        // stale slot (older tag or never used): claim it
+                        const uint64_t prev = (uint64_t)atomicCAS((unsigned long long *)&table[slot],
+                                                                  (unsigned long long)cur,
+                                                                  (unsigned long long)want);
+                        if (prev == cur) {
+                            won = true;
+                            break;
+                        }
+                        cur = prev;
+                    }
+                }
+                overflow = ballot(overflow) != 0ull;
+                const uint64_t winners = ballot(won);
+                const uint32_t nw = (uint32_t)__popcll(winners);
+                if (nw == 0)
+                    continue;
+                if (staged + nw > (uint32_t)kBatchStage)
+                    flush();
+                if (won) {
+                    const uint32_t pos = staged + (uint32_t)lanes_below(winners);
+                    stage_key[wv][pos] = key;
+                    stage_v[wv][pos] = (uint8_t)lane;
+                }
+                staged += nw;
+            }
+        }
+        if (!overflow)
+            flush();
+        if (lane == 0) {
+            if (overflow)
+                atomicOr(&G->overflow, 1u);
+            if (feasible)
+                atomicAdd(&G->successors, (unsigned long long)feasible);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        uint32_t d = 0;
+        if (lane == 0)
+            d = atomicAdd(&J->done, 1u) + 1;
+        d = (uint32_t)__builtin_amdgcn_readlane((int)d, 0);
+        if (d == nchunks && lane == 0)
+            finish_level(a, g, level, count);
+    }
+}
+
+// One block per finished graph: follow the creator of each state back through
+// the stored levels (§3.1; the predecessor is found by a block-wide search).
+__global__ void batch_reconstruct_kernel(BatchGraph *graphs, const int32_t *ids, int32_t *orders)
+{
+    __shared__ unsigned long long found;
+    __shared__ uint64_t S_sh, SL_sh;
+    __shared__ uint64_t idx_sh;
+    const int g = ids[blockIdx.x];
+    BatchGraph *G = &graphs[g];
+    int32_t *order = orders + (size_t)blockIdx.x * 64;
+    const int n = G->n;
+    const int L = G->level;
+    if (threadIdx.x == 0) {
+        S_sh = L > 0 ? G->keys[G->level_off[L]] : 0ull;
+        SL_sh = S_sh;
+        idx_sh = 0;
+    }
+    __syncthreads();
+    for (int i = L; i >= 1; --i) {
+        if (threadIdx.x == 0) {
+            const int v = G->lastv[G->level_off[i] + idx_sh];
+            order[i - 1] = v;
+            S_sh &= ~(1ull << v);
+            found = ~0ull;
+        }
+        __syncthreads();
+        if (i > 1) {
+            const uint64_t b = G->level_off[i - 1];
+            const uint64_t e = G->level_off[i];
+            const uint64_t S = S_sh;
+            for (uint64_t t = b + threadIdx.x; t < e; t += blockDim.x)
+                if (G->keys[t] == S)
+                    atomicMin(&found, (unsigned long long)(t - b));
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            idx_sh = found;
+        __syncthreads();
+        if (i > 1 && idx_sh == ~0ull)
+            break;  // cannot happen for a consistent arena; the host width check rejects it
+    }
+    if (threadIdx.x == 0) {
+        int t = L;
+        for (int v = 0; v < n; ++v)
+            if (!((SL_sh >> v) & 1ull))
+                order[t++] = v;
+        for (; t < 64; ++t)
+            order[t] = -1;
+    }
+}
+
+}  // namespace
+
+int batch_blocks_per_cu()
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel, kBatchBlock, 0) != hipSuccess ||
+        blocks < 1)
+        blocks = 1;
+    return blocks;
+}
+
+hipError_t launch_batch(const BatchArgs &a, unsigned grid_blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_kernel, dim3(grid_blocks), dim3(kBatchBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reconstruct(BatchGraph *graphs, const int32_t *ids, int count, int32_t *orders,
+                                    hipStream_t s)
+{
+    if (count <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(batch_reconstruct_kernel, dim3(count), dim3(256), 0, s, graphs, ids, orders);
+    return hipGetLastError();
+}
+
+}  // namespace twk

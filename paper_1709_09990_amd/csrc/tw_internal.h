@@ -30,12 +30,19 @@ struct LevelArgs {
     LevelCounters *ctr;
     uint32_t max_probe;     // probe-length backstop
     int key_bytes;          // 4 (n <= 32) or 8
+    // Bloom-filter variant (§3.2): used instead of the table when bloom != nullptr
+    uint32_t *bloom;        // bit array of bloom_mask+1 bits, all zero on entry
+    uint64_t bloom_mask;
 };
+
+constexpr int kBloomProbes = 17;     // hash functions per state (§3.2)
+constexpr int kBloomBitsPerState = 24;  // m / n lower bound (§3.2)
 
 constexpr int kBlock = 256;          // 4 waves of 64
 constexpr int kWavesPerBlock = kBlock / 64;
 
 hipError_t launch_fill_empty(void *table, uint64_t bytes, hipStream_t s);
+hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_expand(const LevelArgs &a, unsigned grid_blocks, hipStream_t s);
 hipError_t launch_find(const void *keys, uint64_t count, uint64_t target, int key_bytes,
                        unsigned long long *result, hipStream_t s);

@@ -10,47 +10,76 @@
 // successors S + {v} are inserted into an open-addressing table by atomic
 // compare-and-swap; the lane that claims an empty slot owns the new state,
 // stages it in LDS and the wave appends its staged winners to the next level
-// with one atomic per batch (stream compaction).
+// with one atomic per batch (stream compaction).  The Bloom-filter variant of
+// §3.2 replaces the table insert with 17 double-hashed bit probes.
 #include "tw_internal.h"
+#include "tw_wave.h"
 
 namespace twk {
 namespace {
 
 constexpr int kStage = 512;  // winners a wave stages in LDS before appending
 
-__device__ __forceinline__ uint64_t read_lane64(uint64_t x, int lane)
+__device__ __forceinline__ uint64_t rotl64(uint64_t x, int r)
 {
-    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
-    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
-    return ((uint64_t)hi << 32) | lo;
+    return (x << r) | (x >> (64 - r));
 }
 
-__device__ __forceinline__ uint64_t ballot(bool p)
+__device__ __forceinline__ uint64_t murmur_fmix64(uint64_t k)
 {
-    return __builtin_amdgcn_ballot_w64(p);
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
 }
 
-__device__ __forceinline__ int lanes_below(uint64_t mask)
+// MurmurHash3_x64_128 (Appleby, public domain description) of one 8-byte
+// little-endian key with seed 0: a key shorter than a 16-byte block goes
+// through the tail step only.  Returns the two 64-bit halves.
+__device__ __forceinline__ void murmur3_x64_128_u64(uint64_t key, uint64_t &h1, uint64_t &h2)
 {
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    const uint64_t c1 = 0x87c37b91114253d5ull, c2 = 0x4cf5ad432745937full;
+    h1 = 0;
+    h2 = 0;
+    uint64_t k1 = key;
+    k1 *= c1;
+    k1 = rotl64(k1, 31);
+    k1 *= c2;
+    h1 ^= k1;
+    h1 ^= 8ull;
+    h2 ^= 8ull;
+    h1 += h2;
+    h2 += h1;
+    h1 = murmur_fmix64(h1);
+    h2 = murmur_fmix64(h2);
+    h1 += h2;
+    h2 += h1;
 }
 
-__device__ __forceinline__ void wave_lds_sync()
+// Bloom insert (§3.2): positions H_i = h1 + i*h2 (i = 1..17) mod m.  A bit
+// already seen set is never cleared within a level, so a plain load that reads
+// 1 is final; only bits read as 0 are set with an atomic OR.  The state is new
+// iff some OR found its bit clear.
+__device__ __forceinline__ bool bloom_insert(uint32_t *bits, uint64_t mask, uint64_t key)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Slot of a key: two multiply-xorshift rounds, low bits.
-__device__ __forceinline__ uint64_t slot_of(uint64_t key)
-{
-    uint64_t h = key * 0xD6E8FEB86659FD93ull;
-    h ^= h >> 32;
-    h *= 0xD6E8FEB86659FD93ull;
-    h ^= h >> 32;
-    return h;
+    uint64_t h1, h2;
+    murmur3_x64_128_u64(key, h1, h2);
+    bool fresh = false;
+#pragma unroll
+    for (int i = 1; i <= kBloomProbes; ++i) {
+        const uint64_t pos = (h1 + (uint64_t)i * h2) & mask;
+        uint32_t *w = bits + (pos >> 5);
+        const uint32_t b = 1u << (pos & 31);
+        const uint32_t seen = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!(seen & b)) {
+            const uint32_t old = atomicOr(w, b);
+            if (!(old & b))
+                fresh = true;
+        }
+    }
+    return fresh;
 }
 
 template <typename K>
@@ -69,7 +98,7 @@ __device__ __forceinline__ uint64_t cas<uint64_t>(uint64_t *p, uint64_t e, uint6
                                (unsigned long long)d);
 }
 
-template <typename K>
+template <typename K, bool kBloom>
 __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
 {
     __shared__ K stage_key[kWavesPerBlock][kStage];
@@ -124,26 +153,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
 
         for (int s = 0; s < cnt; ++s) {
             const uint64_t S = read_lane64(mine, s);
-            const bool inS = (S >> lane) & 1ull;
-
-            // Components of G[S]; qacc collects N_out(K) of every K this lane touches.
-            uint64_t qacc = 0;
-            uint64_t rem = S;
-            while (rem) {
-                uint64_t comp = rem & (~rem + 1ull);
-                for (;;) {
-                    const uint64_t nxt = comp | ballot(inS && (Aj & comp) != 0ull);
-                    if (nxt == comp)
-                        break;
-                    comp = nxt;
-                }
-                rem &= ~comp;
-                const uint64_t nout = ballot(!inS && (Aj & comp) != 0ull);
-                if (nout & lanebit)
-                    qacc |= nout;
-            }
-            const uint64_t Q = (Aj | qacc) & ~S & ~lanebit;
-            const bool feas = lane < a.n && !inS && __popcll(Q) <= a.k;
+            const bool feas = lane_feasible(S, Aj, lane, a.n, a.k);
             const uint64_t feas_mask = ballot(feas);
             feasible += (uint64_t)__popcll(feas_mask);
             if (feas_mask == 0ull)
@@ -151,8 +161,11 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
 
             bool won = false;
             const K key = (K)(S | lanebit);
-            if (feas) {
-                uint64_t h = slot_of((uint64_t)key) & a.table_mask;
+            if (kBloom) {
+                if (feas)
+                    won = bloom_insert(a.bloom, a.bloom_mask, (uint64_t)key);
+            } else if (feas) {
+                uint64_t h = slot_hash((uint64_t)key) & a.table_mask;
                 for (uint32_t p = 0;; ++p) {
                     const K old = cas<K>(&table[h], EMPTY, key);
                     if (old == EMPTY) {
@@ -190,6 +203,14 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
 __global__ void fill_empty_kernel(uint4 *p, uint64_t n16)
 {
     const uint4 v = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_zero_kernel(uint4 *p, uint64_t n16)
+{
+    const uint4 v = make_uint4(0u, 0u, 0u, 0u);
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
          i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -236,6 +257,16 @@ hipError_t launch_fill_empty(void *table, uint64_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s)
+{
+    const uint64_t n16 = bytes / 16;
+    if (n16 == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(n16, 256, 8192)), dim3(256), 0, s,
+                       (uint4 *)p, n16);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_counters(LevelCounters *c, hipStream_t s)
 {
     hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, s, c);
@@ -246,10 +277,18 @@ hipError_t launch_expand(const LevelArgs &a, unsigned grid_blocks, hipStream_t s
 {
     if (a.in_count == 0)
         return hipSuccess;
-    if (a.key_bytes == 4)
-        hipLaunchKernelGGL(expand_kernel<uint32_t>, dim3(grid_blocks), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL(expand_kernel<uint64_t>, dim3(grid_blocks), dim3(kBlock), 0, s, a);
+    const bool bloom = a.bloom != nullptr;
+    if (a.key_bytes == 4) {
+        if (bloom)
+            hipLaunchKernelGGL((expand_kernel<uint32_t, true>), dim3(grid_blocks), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((expand_kernel<uint32_t, false>), dim3(grid_blocks), dim3(kBlock), 0, s, a);
+    } else {
+        if (bloom)
+            hipLaunchKernelGGL((expand_kernel<uint64_t, true>), dim3(grid_blocks), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((expand_kernel<uint64_t, false>), dim3(grid_blocks), dim3(kBlock), 0, s, a);
+    }
     return hipGetLastError();
 }
 

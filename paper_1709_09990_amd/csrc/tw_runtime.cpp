@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/tw.h"
+#include "tw_batch.h"
 #include "tw_internal.h"
 
 namespace {
@@ -52,6 +53,7 @@ struct tw_ctx {
     std::vector<Buf> cache;  // free device buffers kept for reuse
     Buf d_adj, d_ctr, d_find;
     Buf table;               // current hash table (reused between levels)
+    Buf bloom;               // Bloom bit array (Bloom variant only)
     LevelCounters *h_ctr = nullptr;      // pinned host mirror
     unsigned long long *h_find = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -370,10 +372,12 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
     for (; i < L; ++i) {
         Level &in = levels.back();
         const uint64_t in_count = in.count;
-        const uint64_t bound = std::min<uint64_t>(binom_sat(n, i + 1),
-                                                  in_count > UINT64_MAX / 64
-                                                      ? UINT64_MAX
-                                                      : in_count * (uint64_t)(n - i));
+        const bool bloom = c->opt.dedup == TW_DEDUP_BLOOM;
+        // every new state comes from a distinct (S, v) pair; exact dedup also
+        // never exceeds C(n, i+1), while concurrent Bloom inserts of one state
+        // may both report it new
+        const uint64_t pairs = in_count > UINT64_MAX / 64 ? UINT64_MAX : in_count * (uint64_t)(n - i);
+        const uint64_t bound = bloom ? pairs : std::min<uint64_t>(binom_sat(n, i + 1), pairs);
         uint64_t guess;
         if (c->opt.capacity_override)
             guess = c->opt.capacity_override;
@@ -394,7 +398,13 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
                 out_cap = guess;
             if (c->opt.max_states)
                 out_cap = std::min<uint64_t>(out_cap, c->opt.max_states);
-            status = acquire(c, c->table, slots * kb);
+            uint64_t bloom_bits = 0;
+            if (bloom) {
+                bloom_bits = pow2_at_least((uint64_t)twk::kBloomBitsPerState * out_cap + 1);
+                status = acquire(c, c->bloom, bloom_bits / 8);
+            } else {
+                status = acquire(c, c->table, slots * kb);
+            }
             if (status == TW_OK)
                 status = acquire(c, scratch_keys, out_cap * kb);
             if (status == TW_OK)
@@ -402,7 +412,10 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
             if (status != TW_OK)
                 goto done;
 
-            HIP_TRY(c, twk::launch_fill_empty(c->table.p, slots * kb, c->stream));
+            if (bloom)
+                HIP_TRY(c, twk::launch_fill_zero(c->bloom.p, bloom_bits / 8, c->stream));
+            else
+                HIP_TRY(c, twk::launch_fill_empty(c->table.p, slots * kb, c->stream));
             HIP_TRY(c, twk::launch_zero_counters((LevelCounters *)c->d_ctr.p, c->stream));
             twk::LevelArgs a{};
             a.in = in.keys.p;
@@ -410,8 +423,10 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
             a.out = scratch_keys.p;
             a.out_lastv = (uint8_t *)scratch_lastv.p;
             a.out_cap = out_cap;
-            a.table = c->table.p;
+            a.table = bloom ? nullptr : c->table.p;
             a.table_mask = slots - 1;
+            a.bloom = bloom ? (uint32_t *)c->bloom.p : nullptr;
+            a.bloom_mask = bloom ? bloom_bits - 1 : 0;
             a.adj = (const uint64_t *)c->d_adj.p;
             a.n = n;
             a.k = k;
@@ -448,7 +463,7 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
                               i + 1, (unsigned long long)c->opt.max_states);
                 goto done;
             }
-            if (out_cap >= bound && slots >= 2 * bound + 64) {
+            if (!bloom && out_cap >= bound && slots >= 2 * bound + 64) {
                 status = fail(c, TW_EDEVICE, "overflow at level %d with capacity at its bound", i + 1);
                 goto done;
             }
@@ -612,6 +627,11 @@ tw_status solve_one(tw_ctx *c, const Graph &g, int32_t *out_tw, int32_t *out_ord
             if (s != TW_OK)
                 return s;
             const int w = fill_in_width(g, out_order);
+            if (c->opt.dedup == TW_DEDUP_BLOOM && w >= lb && w <= k) {
+                // a Bloom NO below k is not certified; the order itself proves tw <= w
+                *out_tw = w;
+                return TW_OK;
+            }
             if (w != k)
                 return fail(c, TW_EDEVICE, "order width %d differs from treewidth %d", w, k);
             *out_tw = k;
@@ -620,6 +640,176 @@ tw_status solve_one(tw_ctx *c, const Graph &g, int32_t *out_tw, int32_t *out_ord
     }
     free_levels(c, levels);
     return fail(c, TW_EDEVICE, "no bound k < n was accepted");
+}
+
+// Runs the persistent batch kernel over batch_ids.  Graphs that finish get
+// their tw and order; graphs whose arena or table filled up are appended to
+// single_ids for the tw_solve path.
+tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<int> &lbs,
+                    const std::vector<int> &ids, int32_t *out_tw, int32_t *out_orders,
+                    const std::vector<size_t> &offs, tw_status *out_status,
+                    std::vector<int> &single_ids, RunStats &rs)
+{
+    if (ids.empty())
+        return TW_OK;
+    const size_t B = ids.size();
+    const uint64_t arena = c->opt.batch_graph_states ? c->opt.batch_graph_states : (1ull << 20);
+    const uint64_t slots = pow2_at_least(arena);
+    uint32_t chunk = c->opt.batch_chunk ? c->opt.batch_chunk : 256u;
+    chunk = std::max<uint32_t>(64u, (chunk + 63u) / 64u * 64u);
+    uint64_t job_cap = 0;
+    for (int t : ids)
+        job_cap += (uint64_t)graphs[(size_t)t].n * (uint64_t)graphs[(size_t)t].n + 1;
+
+    Buf d_graphs, d_jobs, d_q, d_keys, d_lastv, d_table, d_ids, d_orders;
+    auto cleanup = [&]() {
+        release(c, d_graphs);
+        release(c, d_jobs);
+        release(c, d_q);
+        release(c, d_keys);
+        release(c, d_lastv);
+        release(c, d_table);
+        release(c, d_ids);
+        release(c, d_orders);
+    };
+    tw_status s = acquire(c, d_graphs, B * sizeof(twk::BatchGraph));
+    const size_t job_bytes = (job_cap * sizeof(twk::BatchJob) + 15) / 16 * 16;
+    if (s == TW_OK)
+        s = acquire(c, d_jobs, job_bytes);
+    if (s == TW_OK)
+        s = acquire(c, d_q, sizeof(twk::BatchQueue));
+    if (s == TW_OK)
+        s = acquire(c, d_keys, B * arena * sizeof(uint64_t));
+    if (s == TW_OK)
+        s = acquire(c, d_lastv, B * arena);
+    if (s == TW_OK)
+        s = acquire(c, d_table, B * slots * sizeof(uint64_t));
+    if (s == TW_OK)
+        s = acquire(c, d_ids, B * sizeof(int32_t));
+    if (s == TW_OK)
+        s = acquire(c, d_orders, B * 64 * sizeof(int32_t));
+    if (s != TW_OK) {
+        cleanup();
+        return s;
+    }
+    std::vector<twk::BatchGraph> hg(B);
+    std::vector<twk::BatchJob> hj(B);
+    for (size_t b = 0; b < B; ++b) {
+        const Graph &g = graphs[(size_t)ids[b]];
+        twk::BatchGraph &G = hg[b];
+        std::memset(&G, 0, sizeof G);
+        for (int j = 0; j < g.n; ++j)
+            G.adj[j] = g.rows[j];
+        G.keys = (uint64_t *)d_keys.p + b * arena;
+        G.lastv = (uint8_t *)d_lastv.p + b * arena;
+        G.arena_cap = arena;
+        G.table = (uint64_t *)d_table.p + b * slots;
+        G.table_mask = slots - 1;
+        G.level_off[0] = 0;
+        G.level_off[1] = 1;
+        G.status = twk::kBatchRunning;
+        G.n = g.n;
+        G.k = lbs[(size_t)ids[b]];
+        G.level = 0;
+        G.L = g.n - G.k - 1;
+        G.tw = -1;
+        G.tag = 1;
+        G.decisions = 1;
+        twk::BatchJob &J = hj[b];
+        std::memset(&J, 0, sizeof J);
+        J.graph = (int32_t)b;
+        J.level = 0;
+        J.begin = 0;
+        J.count = 1;
+        J.nchunks = 1;
+        J.ready = 1;
+    }
+    twk::BatchQueue hq{};
+    hq.head = 0;
+    hq.tail = B;
+    hq.capacity = job_cap;
+    hq.active = (uint32_t)B;
+    hq.abort = 0;
+    // tables start with tag 0 (never a live tag); jobs beyond the first B are not ready
+    HIP_TRY(c, twk::launch_fill_zero(d_table.p, B * slots * sizeof(uint64_t), c->stream));
+    HIP_TRY(c, twk::launch_fill_zero(d_jobs.p, job_bytes, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d_graphs.p, hg.data(), B * sizeof(twk::BatchGraph), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d_jobs.p, hj.data(), B * sizeof(twk::BatchJob), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d_q.p, &hq, sizeof hq, hipMemcpyHostToDevice, c->stream));
+
+    twk::BatchArgs a{};
+    a.graphs = (twk::BatchGraph *)d_graphs.p;
+    a.jobs = (twk::BatchJob *)d_jobs.p;
+    a.q = (twk::BatchQueue *)d_q.p;
+    a.chunk = chunk;
+    a.max_probe = 1u << 14;
+    a.max_load = 0.7f;
+    a.spin_limit = 20u * 1000u * 1000u;
+    const unsigned grid = (unsigned)(c->cu_count * twk::batch_blocks_per_cu());
+    if (c->opt.timing)
+        HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+    HIP_TRY(c, twk::launch_batch(a, grid, c->stream));
+    if (c->opt.timing)
+        HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(hg.data(), d_graphs.p, B * sizeof(twk::BatchGraph), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&hq, d_q.p, sizeof hq, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    rs.launches++;
+    if (c->opt.timing) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        rs.kernel_seconds += ms * 1e-3;
+    }
+    if (hq.abort) {
+        cleanup();
+        return fail(c, TW_EDEVICE, "batch kernel aborted (work-queue wait bound or job capacity)");
+    }
+    std::vector<int32_t> done_local;
+    for (size_t b = 0; b < B; ++b) {
+        const twk::BatchGraph &G = hg[b];
+        rs.states_expanded += G.states;
+        rs.expansions += G.expansions;
+        rs.successors += G.successors;
+        rs.levels += G.levels_run;
+        rs.decisions += G.decisions;
+        rs.peak = std::max<uint64_t>(rs.peak, G.peak);
+        rs.unique += G.unique;
+        if (G.status == twk::kBatchDone)
+            done_local.push_back((int32_t)b);
+        else
+            single_ids.push_back(ids[b]);
+    }
+    if (!done_local.empty()) {
+        HIP_TRY(c, hipMemcpyAsync(d_ids.p, done_local.data(), done_local.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, twk::launch_batch_reconstruct((twk::BatchGraph *)d_graphs.p, (const int32_t *)d_ids.p,
+                                                 (int)done_local.size(), (int32_t *)d_orders.p, c->stream));
+        std::vector<int32_t> orders(done_local.size() * 64);
+        HIP_TRY(c, hipMemcpyAsync(orders.data(), d_orders.p, orders.size() * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (size_t q = 0; q < done_local.size(); ++q) {
+            const int b = done_local[q];
+            const int t = ids[(size_t)b];
+            const Graph &g = graphs[(size_t)t];
+            int32_t *o = out_orders + offs[(size_t)t];
+            for (int v = 0; v < g.n; ++v)
+                o[v] = orders[q * 64 + (size_t)v];
+            const int w = fill_in_width(g, o);
+            if (w != hg[(size_t)b].tw) {
+                out_status[t] = fail(c, TW_EDEVICE, "batch graph %d: order width %d != treewidth %d", t, w,
+                                     hg[(size_t)b].tw);
+                continue;
+            }
+            out_tw[t] = hg[(size_t)b].tw;
+            out_status[t] = TW_OK;
+        }
+    }
+    cleanup();
+    return TW_OK;
 }
 
 double now_s()
@@ -659,7 +849,7 @@ tw_status tw_ctx_create(const tw_options *options, tw_ctx **out)
         std::memcpy(&c->opt, options, sz);
     }
     c->opt.struct_size = sizeof(tw_options);
-    if (c->opt.dedup != TW_DEDUP_EXACT) {
+    if (c->opt.dedup != TW_DEDUP_EXACT && c->opt.dedup != TW_DEDUP_BLOOM) {
         delete c;
         return TW_EINVAL;
     }
@@ -711,6 +901,7 @@ void tw_ctx_destroy(tw_ctx *c)
     release(c, c->d_ctr);
     release(c, c->d_find);
     release(c, c->table);
+    release(c, c->bloom);
     drop_cache(c);
     if (c->h_ctr)
         (void)hipHostFree(c->h_ctr);
@@ -810,16 +1001,42 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
         return fail(c, TW_EDEVICE, "hipSetDevice failed");
     const double t0 = now_s();
     RunStats rs;
+    std::vector<Graph> graphs(count);
+    std::vector<size_t> offs(count);
+    std::vector<int> lbs(count, 0);
+    std::vector<int> batch_ids;   // graphs that go into the persistent launch
+    std::vector<int> single_ids;  // graphs solved one at a time
     size_t off = 0;
     for (uint32_t t = 0; t < count; ++t) {
-        Graph g;
-        tw_status s = validate(c, &gs[t], g);
-        if (s == TW_OK)
-            s = solve_one(c, g, &out_tw[t], out_orders + off, rs);
+        offs[t] = off;
+        off += gs[t].n;
+        out_tw[t] = -1;
+        out_status[t] = validate(c, &gs[t], graphs[t]);
+        if (out_status[t] != TW_OK)
+            continue;
+        const Graph &g = graphs[t];
+        lbs[t] = mmw_bound(g);
+        if (lbs[t] >= g.n - 1) {
+            // tw = n - 1: decide(n - 1) needs no level; any order has width n - 1
+            out_tw[t] = g.n - 1;
+            for (int v = 0; v < g.n; ++v)
+                out_orders[offs[t] + v] = v;
+            rs.decisions++;
+        } else if (g.n <= twk::kBatchMaxN && c->opt.dedup == TW_DEDUP_EXACT) {
+            batch_ids.push_back((int)t);
+        } else {
+            single_ids.push_back((int)t);
+        }
+    }
+    tw_status st = batch_run(c, graphs, lbs, batch_ids, out_tw, out_orders, offs, out_status,
+                             single_ids, rs);
+    if (st != TW_OK)
+        return st;
+    for (int t : single_ids) {
+        tw_status s = solve_one(c, graphs[(size_t)t], &out_tw[t], out_orders + offs[(size_t)t], rs);
         out_status[t] = s;
         if (s != TW_OK)
             out_tw[t] = -1;
-        off += gs[t].n;
         if (s == TW_EDEVICE)
             return s;
     }

@@ -248,3 +248,70 @@ def test_batch_equals_single(oracle, ctx):
         single, _, _ = ctx.solve(rows)
         assert tw == single
         assert oracle.order_width(rows, order) == tw
+
+
+def _bloom_ctx():
+    from paper_1709_09990_amd import tw as T
+    return T.Context(device=0, dedup=T.TW_DEDUP_BLOOM)
+
+
+def test_bloom_levels_subset_of_exact(oracle):
+    """Bloom variant (§3.2): every level is a subset of the exact level (false
+    positives only drop states), and with m/n >= 24 bits and 17 probes the
+    losses stay near the (1 - e^(-17/24))^17 ~ 1e-5 per-insert rate."""
+    cases = [(G.workload_single_small(1001), None), (G.edgeless(22), 0), (G.gnp(30, 0.3, 12007), None)]
+    with _bloom_ctx() as bctx:
+        for rows, k in cases:
+            if k is None:
+                k = oracle.treewidth_bfs(rows, oracle.mmw(rows))
+            _, exact, _ = oracle.decide(rows, k)
+            _, levels = bctx.trace_decide(rows, k)
+            dropped = 0
+            total = 0
+            for lv in levels:
+                got = np.unique(lv.states)
+                ref = exact[lv.level]
+                assert np.isin(got, ref).all(), (k, lv.level)
+                dropped += len(ref) - len(got)
+                total += len(ref)
+            assert dropped <= 1e-4 * total + 10, (dropped, total)
+
+
+def test_bloom_solve_validated(oracle):
+    with _bloom_ctx() as bctx:
+        for seed in (1001, 1002, 1003):
+            rows = G.workload_single_small(seed)
+            tw, _ = oracle.subset_dp(rows)
+            got, order, _ = bctx.solve(rows)
+            # a Bloom answer is an upper bound proved by its order; here it is exact
+            assert oracle.order_width(rows, order) == got
+            assert got == tw
+
+
+def test_batch_persistent_matches_oracle(oracle):
+    """One persistent launch over graphs of uneven n (8..30): every treewidth
+    equals the oracle's and every order has exactly that width."""
+    from paper_1709_09990_amd import tw as T
+    graphs = G.workload_batch(96, seed0=32000, n_lo=8, n_hi=30)
+    want = [oracle.treewidth_bfs(r, oracle.mmw(r)) for r in graphs]
+    with T.Context(device=0, timing=True) as c:
+        tws, orders, status, st = c.solve_batch(graphs)
+    assert list(status) == [0] * len(graphs)
+    assert list(tws) == want
+    for rows, tw, order in zip(graphs, tws, orders):
+        assert oracle.order_width(rows, order) == tw
+    assert st["launches"] >= 1
+
+
+def test_batch_fallback_on_small_arena(oracle):
+    """A tiny per-graph arena forces graphs out of the persistent launch onto
+    the single-graph path; answers are unchanged."""
+    from paper_1709_09990_amd import tw as T
+    graphs = G.workload_batch(24, seed0=33000, n_lo=12, n_hi=28)
+    want = [oracle.treewidth_bfs(r, oracle.mmw(r)) for r in graphs]
+    with T.Context(device=0, batch_graph_states=512, batch_chunk=64) as c:
+        tws, orders, status, _ = c.solve_batch(graphs)
+    assert list(status) == [0] * len(graphs)
+    assert list(tws) == want
+    for rows, tw, order in zip(graphs, tws, orders):
+        assert oracle.order_width(rows, order) == tw
