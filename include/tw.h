@@ -161,6 +161,46 @@ tw_status tw_mmw(const tw_graph *g, int32_t *out_lb);
  * not a permutation of 0..n-1.  Host only. */
 tw_status tw_order_width(const tw_graph *g, const int32_t *order, int32_t *out_width);
 
+/* ---------------------------------------------------------------------------
+ * Learned start bound: a small message-passing network (not from the paper)
+ * that predicts a graph's treewidth and the size of the largest level of its
+ * certifying search.  The exact search always decides the answer; the network
+ * only picks where the search starts and how much memory a graph gets.
+ *
+ *   node features   [1, deg(v)/8, core(v)/8, n/64]     (core = core number)
+ *   3 layers        H' = ReLU(H Ws^T + (A H) Wn^T + b), hidden width 64
+ *   readout         [sum_v H_v ; max_v H_v] -> y = Wo r + bo, two outputs:
+ *                   y0 ~ tw / n,  y1 ~ log2(peak level + 1) / 32
+ *
+ * Parameters are tw_mpnn_param_count() floats, in this order: for each layer
+ * Ws [64][64] (row = output), Wn [64][64], b [64]; then Wo [2][128], bo [2].
+ * Products run as bfloat16 MFMA with float32 accumulation (operands H, A H,
+ * Ws, Wn, and in the backward pass dZ and dZ Wn, rounded to bfloat16, ties
+ * to even); the master parameters and Adam moments stay float32.
+ * ------------------------------------------------------------------------- */
+typedef struct tw_mpnn tw_mpnn;
+
+uint32_t tw_mpnn_param_count(void);
+/* Host only: the 64 x 4 node features of g (rows beyond n are zero). */
+tw_status tw_mpnn_features(const tw_graph *g, float *out);
+/* A network on device with the given host parameters (copied); stream may be NULL. */
+tw_status tw_mpnn_create(int device, void *stream, const float *params, tw_mpnn **out);
+void tw_mpnn_destroy(tw_mpnn *m);
+/* Replace the parameters (resets the Adam moments); read them back. */
+tw_status tw_mpnn_set_params(tw_mpnn *m, const float *params);
+tw_status tw_mpnn_get_params(tw_mpnn *m, float *params);
+/* out[2*t + j] = output j for graph t. */
+tw_status tw_mpnn_predict(tw_mpnn *m, const tw_graph *gs, uint32_t count, float *out);
+/* Mean squared error over graphs and both outputs against targets[2*t + j],
+ * and its gradient (out_grads: tw_mpnn_param_count() floats).  Per-graph
+ * gradients are summed in graph order (deterministic). */
+tw_status tw_mpnn_gradients(tw_mpnn *m, const tw_graph *gs, uint32_t count, const float *targets,
+                            float *out_loss, float *out_grads);
+/* One AdamW step (beta 0.9 / 0.999, eps 1e-8; weight decay on the matrices
+ * only) on the loss above; *out_loss (nullable) is the loss before the step. */
+tw_status tw_mpnn_train_step(tw_mpnn *m, const tw_graph *gs, uint32_t count, const float *targets, float lr,
+                             float weight_decay, float *out_loss);
+
 const char *tw_status_str(tw_status s);
 /* Message of the last failure on ctx (empty string if none); valid until the next call. */
 const char *tw_last_error(const tw_ctx *ctx);

@@ -81,6 +81,9 @@ _SINK = ctypes.CFUNCTYPE(None, ctypes.POINTER(_LevelRecord), ctypes.c_void_p)
 EXPORTS = (
     "tw_ctx_create", "tw_ctx_destroy", "tw_decide", "tw_solve", "tw_solve_batch",
     "tw_trace_decide", "tw_mmw", "tw_order_width", "tw_status_str", "tw_last_error",
+    "tw_mpnn_param_count", "tw_mpnn_features", "tw_mpnn_create", "tw_mpnn_destroy",
+    "tw_mpnn_set_params", "tw_mpnn_get_params", "tw_mpnn_predict", "tw_mpnn_gradients",
+    "tw_mpnn_train_step",
 )
 
 _lib = None
@@ -111,8 +114,22 @@ def load():
     L.tw_status_str.restype = ctypes.c_char_p
     L.tw_last_error.argtypes = [ctypes.c_void_p]
     L.tw_last_error.restype = ctypes.c_char_p
+    f32p = P(ctypes.c_float)
+    L.tw_mpnn_param_count.argtypes = []
+    L.tw_mpnn_param_count.restype = ctypes.c_uint32
+    L.tw_mpnn_features.argtypes = [P(_Graph), f32p]
+    L.tw_mpnn_create.argtypes = [ctypes.c_int, ctypes.c_void_p, f32p, P(ctypes.c_void_p)]
+    L.tw_mpnn_destroy.argtypes = [ctypes.c_void_p]
+    L.tw_mpnn_destroy.restype = None
+    L.tw_mpnn_set_params.argtypes = [ctypes.c_void_p, f32p]
+    L.tw_mpnn_get_params.argtypes = [ctypes.c_void_p, f32p]
+    L.tw_mpnn_predict.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_uint32, f32p]
+    L.tw_mpnn_gradients.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_uint32, f32p, f32p, f32p]
+    L.tw_mpnn_train_step.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_uint32, f32p, ctypes.c_float,
+                                     ctypes.c_float, f32p]
     for name in ("tw_ctx_create", "tw_decide", "tw_solve", "tw_solve_batch", "tw_trace_decide",
-                 "tw_mmw", "tw_order_width"):
+                 "tw_mmw", "tw_order_width", "tw_mpnn_features", "tw_mpnn_create", "tw_mpnn_set_params",
+                 "tw_mpnn_get_params", "tw_mpnn_predict", "tw_mpnn_gradients", "tw_mpnn_train_step"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -262,3 +279,94 @@ class Context:
         yes = ctypes.c_int32(0)
         self._check(self._L.tw_trace_decide(self._h, ctypes.byref(g), int(k), cb, None, ctypes.byref(yes)))
         return bool(yes.value), levels
+
+
+def _graph_array(graphs):
+    arrs = [np.ascontiguousarray(np.asarray(r, dtype=np.uint64)) for r in graphs]
+    gs = (_Graph * max(1, len(arrs)))()
+    for t, a in enumerate(arrs):
+        gs[t].n = len(a)
+        gs[t].adj = a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    return gs, arrs
+
+
+def mpnn_param_count() -> int:
+    return int(load().tw_mpnn_param_count())
+
+
+def mpnn_features(rows) -> np.ndarray:
+    L = load()
+    g, keep = _graph(rows)
+    out = np.zeros((64, 4), dtype=np.float32)
+    st = L.tw_mpnn_features(ctypes.byref(g), out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    if st != TW_OK:
+        raise TwError(st, "tw_mpnn_features")
+    return out
+
+
+class Mpnn:
+    """The learned start-bound network on the device (bf16 MFMA kernels)."""
+
+    def __init__(self, params: np.ndarray, device: int = 0):
+        L = load()
+        self._L = L
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != mpnn_param_count():
+            raise ValueError("wrong parameter count")
+        h = ctypes.c_void_p()
+        self._check(L.tw_mpnn_create(device, None, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                     ctypes.byref(h)))
+        self._h = h
+
+    def _check(self, st):
+        if st != TW_OK:
+            raise TwError(st, self._L.tw_status_str(st).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.tw_mpnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(mpnn_param_count(), dtype=np.float32)
+        self._check(self._L.tw_mpnn_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self._L.tw_mpnn_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def predict(self, graphs) -> np.ndarray:
+        gs, keep = _graph_array(graphs)
+        out = np.zeros((max(1, len(graphs)), 2), dtype=np.float32)
+        self._check(self._L.tw_mpnn_predict(self._h, gs, len(graphs),
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out[:len(graphs)]
+
+    def gradients(self, graphs, targets):
+        gs, keep = _graph_array(graphs)
+        t = np.ascontiguousarray(targets, dtype=np.float32)
+        loss = ctypes.c_float(0)
+        g = np.zeros(mpnn_param_count(), dtype=np.float32)
+        self._check(self._L.tw_mpnn_gradients(self._h, gs, len(graphs),
+                                              t.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                              ctypes.byref(loss), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return loss.value, g
+
+    def train_step(self, graphs, targets, lr: float, weight_decay: float = 0.0) -> float:
+        gs, keep = _graph_array(graphs)
+        t = np.ascontiguousarray(targets, dtype=np.float32)
+        loss = ctypes.c_float(0)
+        self._check(self._L.tw_mpnn_train_step(self._h, gs, len(graphs),
+                                               t.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                               float(lr), float(weight_decay), ctypes.byref(loss)))
+        return loss.value

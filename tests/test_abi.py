@@ -72,3 +72,15 @@ def test_invalid_graphs_rejected_on_host(rows):
     with pytest.raises(T.TwError) as e:
         T.mmw(rows)
     assert e.value.status == T.TW_EINVAL
+
+
+def test_network_features_match_reference():
+    """Node features of the learned start bound, host side, against the
+    independent reference implementation (degree and core number)."""
+    from oracle import mpnn_ref as M
+    for t in range(40):
+        rows = G.workload_batch(1, seed0=9000 + t, n_lo=5, n_hi=64)[0]
+        X, _, _ = M.features(rows)
+        got = T.mpnn_features(rows)
+        assert np.allclose(got, X[:, :4].astype(np.float32))
+    assert T.mpnn_param_count() == M.N_PARAMS
