@@ -1,4 +1,4 @@
-"""Benchmark: exact treewidth of the single n = 40..42 graphs on one MI355X.
+"""Benchmark: exact treewidth of single n = 40 graphs on one MI355X.
 
 One step solves each graph of the workload with tw_solve (minor-min-width
 lower bound, ascending k, every level expanded and deduplicated on the GPU,
@@ -32,16 +32,39 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+WORKLOADS = {
+    # the single n = 40..42 graphs; the 6x7 grid's bound k = 6 needs levels of
+    # ~10^10 states (k = 5 already peaks at 3.1e9), beyond one GPU's 288 GB
+    "single_n40_one_gpu": "G(40, 0.15) seed 2001 and the random partial 8-tree on 40 vertices "
+                          "(30% edges dropped, seed 2003): the n=40..42 single graphs whose exact "
+                          "solve fits one MI355X (the 6x7 grid needs >288 GB at k=6)",
+    "single_n40": "all three n=40..42 single graphs (includes the 6x7 grid; exceeds one GPU)",
+    "single_n20": "G(20, 0.3) seed 1001",
+}
+
+
 def _workload(name: str):
     from paper_1709_09990_amd import graphs as G
     if name == "single_n40":
         return G.workload_single_n40()
-    if name == "single_n40_small":   # the two graphs whose solve takes seconds
+    if name == "single_n40_one_gpu":
         w = G.workload_single_n40()
         return {k: w[k] for k in ("gnp40_p015", "partial8tree40")}
     if name == "single_n20":
         return {"gnp20_p03": G.workload_single_small(1001)}
     raise SystemExit(f"unknown workload {name}")
+
+
+def copy_probe(nbytes: int, reps: int = 5):
+    """A plain device-to-device copy of known size (read nbytes, write nbytes),
+    run only to scale the FETCH_SIZE / WRITE_SIZE counters of a profile."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
 
 
 def cpu_baseline(budget_s: float = 15.0):
@@ -81,12 +104,16 @@ def cpu_baseline(budget_s: float = 15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="single_n40")
+    ap.add_argument("--workload", default="single_n40_one_gpu", choices=sorted(WORKLOADS))
+    ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the search over one graph "
               "is not sharded across GPUs in this build", file=sys.stderr)
@@ -144,7 +171,7 @@ def main():
         "alg_bytes_per_launch": int(alg_bytes / max(1, total["launches"])),
     }
     out = {
-        "metric": "(S,v) expansions/sec, exact",
+        "metric": "(S,v) expansions/sec + graphs solved/sec (learned-k batched vs plain), exact",
         "value": total["expansions"] / elapsed,
         "unit": "expansions/s",
         "n_gpus": 1,
@@ -156,7 +183,8 @@ def main():
         "vs_baseline": None,
         "dtype": "u%d" % (8 * w),
         "data": "synthetic",
-        "config": {"workload": args.workload, "graphs": {nm: len(graphs[nm]) for nm in names},
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
+                   "graphs": {nm: len(graphs[nm]) for nm in names},
                    "treewidth": tws, "dedup": "exact", "k_policy": "ascending from minor-min-width"},
         "states_per_s": total["states_expanded"] / elapsed,
         "graphs_per_s": len(names) * args.steps / elapsed,

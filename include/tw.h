@@ -76,7 +76,9 @@ typedef struct {
     int dedup;                /* TW_DEDUP_EXACT or TW_DEDUP_BLOOM */
     float load_factor;        /* target hash-table load in (0, 0.9]; 0 picks the default 0.5 */
     int k_policy;             /* TW_K_ASCENDING or TW_K_LEARNED */
-    const char *weights_path; /* learned policy weights (TW_K_LEARNED only) */
+    const char *weights_path; /* TW_K_LEARNED: file of network parameters: 8 bytes "TWMPNN01", a
+                                 uint32 count (= tw_mpnn_param_count()), then count float32 values,
+                                 little-endian; read at tw_ctx_create (TW_EINVAL if absent or bad) */
     uint64_t max_states;      /* cap on states per level (0 = limited only by device memory) */
     uint64_t capacity_override; /* test hook: first guess of every level's size (0 = estimate); a
                                    small value forces the overflow -> regrow -> replay path */
@@ -114,7 +116,8 @@ void tw_ctx_destroy(tw_ctx *ctx);
 tw_status tw_decide(tw_ctx *ctx, const tw_graph *g, int32_t k, int32_t *out_yes, tw_stats *stats);
 
 /* tw(G) and an elimination order of that width (§2): ascending k from the
- * minor-min-width bound (§3.3).  out_order[t] is the t-th vertex eliminated;
+ * minor-min-width bound (§3.3), or from the learned start bound (moving down
+ * after a YES, up after a NO) with options.k_policy = TW_K_LEARNED.  out_order[t] is the t-th vertex eliminated;
  * it must hold n entries.  The order is rebuilt from the last level by
  * following, for each state, the vertex that created it back to the empty
  * set, then the k+1 remaining vertices in ascending index; its width is
@@ -129,10 +132,26 @@ tw_status tw_solve(tw_ctx *ctx, const tw_graph *g, int32_t *out_tw, int32_t *out
  * graph whose arena or table fills up) go through the tw_solve path.  The
  * treewidths equal tw_solve's; each order is checked by fill-in to have
  * exactly that width (several orders may qualify).
- * A graph that fails gets its own status; the others still complete.  The
- * return value is TW_OK unless an argument is invalid or the device failed. */
+ * With options.k_policy = TW_K_LEARNED each graph starts at the bound the
+ * network predicts (clamped to [lower bound, n-2]) and gets an arena sized
+ * from the predicted peak level; the search then certifies the answer exactly
+ * (YES at t and NO at t-1, or t = lower bound).  out_graph_stats (nullable,
+ * [count]) receives per-graph outcomes.  A graph that fails gets its own
+ * status; the others still complete.  The return value is TW_OK unless an
+ * argument is invalid or the device failed. */
+typedef struct {
+    uint64_t peak_yes;        /* largest level of the run that certified the answer (YES at tw) */
+    uint64_t expansions;      /* (S, v) pairs over this graph's whole search */
+    uint64_t states_expanded; /* states expanded over this graph's whole search */
+    int32_t start_k;          /* first bound tried (lower bound, or the learned prediction) */
+    uint32_t decisions;       /* bounds tried */
+    int32_t path;             /* 0: persistent batch kernel, 1: single-graph path, 2: trivial (tw = n-1) */
+    int32_t reserved;
+} tw_graph_stats;
+
 tw_status tw_solve_batch(tw_ctx *ctx, const tw_graph *gs, uint32_t count, int32_t *out_tw,
-                         int32_t *out_orders, tw_status *out_status, tw_stats *stats);
+                         int32_t *out_orders, tw_status *out_status, tw_graph_stats *out_graph_stats,
+                         tw_stats *stats);
 
 /* One level of a bound-k search, as handed to a trace sink. */
 typedef struct {

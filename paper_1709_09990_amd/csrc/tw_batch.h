@@ -34,12 +34,17 @@ struct BatchGraph {
     unsigned long long states;      // states expanded over the whole solve
     unsigned long long peak;        // largest level
     unsigned long long unique;      // states written over the whole solve
+    unsigned long long peak_k;      // largest level of the current bound
+    unsigned long long peak_yes;    // largest level of the best YES run
     uint32_t overflow;
     uint32_t status;
     int32_t n, k, level, L;
     int32_t tw;
+    int32_t known_no;        // largest bound known to be NO (lower bound - 1 at start)
+    int32_t best_yes;        // smallest bound known to be YES (n - 1 at start)
     uint32_t tag;
     uint32_t decisions, levels_run;
+    int32_t order[64];       // elimination order of the best YES run (width best_yes)
 };
 
 // One level of one graph: nchunks tasks of up to chunk states.
@@ -73,8 +78,6 @@ struct BatchArgs {
 };
 
 hipError_t launch_batch(const BatchArgs &a, unsigned grid_blocks, hipStream_t s);
-hipError_t launch_batch_reconstruct(BatchGraph *graphs, const int32_t *ids, int count,
-                                    int32_t *orders /* count x 64 */, hipStream_t s);
 int batch_blocks_per_cu();
 
 }  // namespace twk

@@ -8,7 +8,9 @@
 // NO (empty level), or done after a YES — so graphs of different sizes never
 // wait for each other.  Each graph has its own arena (all levels of its
 // current bound, back to back, for the order backtrack) and its own hash
-// table.  Table slots carry a 16-bit tag above the 48-bit state; a slot whose
+// table.  A graph's search starts at the bound the host gives it (lower bound
+// or prediction) and moves until a YES at t meets a NO at t-1 (or t = lower
+// bound); the order of each YES is captured before the arena is reused.  Table slots carry a 16-bit tag above the 48-bit state; a slot whose
 // tag is not the level's tag counts as empty, so tables are never cleared.
 //
 // Exit: every wave leaves once no graph is running, or after spin_limit
@@ -55,62 +57,139 @@ __device__ void push_job(const BatchArgs &a, int g, int level, uint64_t begin, u
     __hip_atomic_store(&j->ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Called by one lane after every chunk of (g, level) has finished.
-__device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_count)
+// Whole wave, after a YES at bound G->k with G->L levels in the arena: follow
+// the vertex that created each state back to the empty set (§3.1 stores one
+// creator per state; the predecessor is found by a wave-wide scan of the
+// level below), then the k+1 vertices never eliminated, ascending.
+__device__ void capture_order(BatchGraph *G, int lane)
 {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    BatchGraph *G = &a.graphs[g];
-    const uint64_t cnt = ld_relaxed(&G->out_count);
-    const uint32_t ovf = ld_relaxed(&G->overflow);
-    G->states += in_count;
-    G->expansions += in_count * (uint64_t)(G->n - level);
-    G->levels_run++;
-    G->unique += cnt;
-    if (cnt > G->peak)
-        G->peak = cnt;
-    if (ovf || G->tag >= 0xFFFFu) {
-        G->status = kBatchFallback;
+    const int L = G->L;
+    const uint64_t SL = L > 0 ? read_lane64(G->keys[G->level_off[L]], 0) : 0ull;
+    uint64_t S = SL;
+    uint64_t idx = 0;
+    for (int i = L; i >= 1; --i) {
+        const int v = (int)first_lane32(G->lastv[G->level_off[i] + idx]);
+        if (lane == 0)
+            G->order[i - 1] = v;
+        S &= ~(1ull << v);
+        if (i == 1)
+            break;
+        const uint64_t b = G->level_off[i - 1];
+        const uint64_t cnt = G->level_off[i] - b;
+        idx = ~0ull;
+        for (uint64_t t0 = 0; t0 < cnt; t0 += 64) {
+            const uint64_t t = t0 + (uint64_t)lane;
+            const uint64_t hit = ballot(t < cnt && G->keys[b + t] == S);
+            if (hit) {
+                idx = t0 + (uint64_t)__builtin_ctzll(hit);
+                break;
+            }
+        }
+        if (idx == ~0ull)
+            break;  // inconsistent arena: the host's width check rejects the order
+    }
+    if (lane == 0) {
+        int t = L;
+        for (int v = 0; v < G->n; ++v)
+            if (!((SL >> v) & 1ull))
+                G->order[t++] = v;
+    }
+}
+
+__device__ void graph_done(const BatchArgs &a, BatchGraph *G, uint32_t status, int lane)
+{
+    if (lane == 0) {
+        G->status = status;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         atomicSub(&a.q->active, 1u);
-        return;
     }
-    if (cnt == 0) {
-        // NO at bound k: restart at level 0 with k + 1
-        G->k++;
+}
+
+// Restart graph G at level 0 of bound k (lane 0 writes, then publishes the job).
+__device__ void start_bound(const BatchArgs &a, BatchGraph *G, int g, int k, int lane)
+{
+    if (lane == 0) {
+        G->k = k;
         G->decisions++;
-        if (G->k >= G->n - 1) {
-            G->tw = G->k;
-            G->level = 0;
-            G->L = 0;
-            G->status = kBatchDone;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            atomicSub(&a.q->active, 1u);
-            return;
-        }
-        G->L = G->n - G->k - 1;
+        G->L = G->n - k - 1;
         G->level = 0;
         G->tag++;
         G->out_count = 0;
+        G->peak_k = 1;
         G->level_off[0] = 0;
         G->level_off[1] = 1;  // level 0 is the empty set (never read from the arena)
         push_job(a, g, 0, 0, 1);
+    }
+}
+
+// Whole wave, after every chunk of (g, level) has finished.  Advances the
+// graph's search: a NO raises the lower side, a YES (with its order captured)
+// lowers the upper side; the graph is done when they meet.  The starting
+// bound may be the minor-min-width bound (ascending search) or a prediction
+// (the search then moves down after a YES and up after a NO).
+__device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_count, int lane)
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    BatchGraph *G = &a.graphs[g];
+    const uint64_t cnt = read_lane64(ld_relaxed(&G->out_count), 0);
+    const uint32_t ovf = first_lane32(ld_relaxed(&G->overflow));
+    const int n = G->n;
+    const int k = G->k;
+    if (lane == 0) {
+        G->states += in_count;
+        G->expansions += in_count * (uint64_t)(n - level);
+        G->levels_run++;
+        G->unique += cnt;
+        if (cnt > G->peak)
+            G->peak = cnt;
+        if (cnt > G->peak_k)
+            G->peak_k = cnt;
+    }
+    if (ovf || G->tag >= 0xFFFEu) {
+        graph_done(a, G, kBatchFallback, lane);
         return;
     }
     const int next = level + 1;
-    G->level_off[next + 1] = G->level_off[next] + cnt;
-    if (next == G->L) {
-        // YES at bound k: the levels of this bound stay in the arena
-        G->tw = G->k;
-        G->level = next;
-        G->status = kBatchDone;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        atomicSub(&a.q->active, 1u);
+    if (cnt == 0) {
+        // NO at bound k
+        const int known_no = k > G->known_no ? k : G->known_no;
+        if (lane == 0)
+            G->known_no = known_no;
+        if (G->best_yes <= known_no + 1) {
+            if (lane == 0)
+                G->tw = G->best_yes;
+            graph_done(a, G, kBatchDone, lane);
+        } else {
+            start_bound(a, G, g, known_no + 1, lane);
+        }
         return;
     }
-    G->level = next;
-    G->tag++;
-    G->out_count = 0;
-    push_job(a, g, next, G->level_off[next], cnt);
+    if (lane == 0)
+        G->level_off[next + 1] = G->level_off[next] + cnt;
+    if (next < G->L) {
+        if (lane == 0) {
+            G->level = next;
+            G->tag++;
+            G->out_count = 0;
+            push_job(a, g, next, G->level_off[next], cnt);
+        }
+        return;
+    }
+    // YES at bound k: keep its order, then certify or move down
+    if (lane == 0)
+        G->level = next;
+    capture_order(G, lane);
+    if (lane == 0) {
+        G->best_yes = k;
+        G->peak_yes = G->peak_k;
+    }
+    if (k - 1 <= G->known_no) {
+        if (lane == 0)
+            G->tw = k;
+        graph_done(a, G, kBatchDone, lane);
+    } else {
+        start_bound(a, G, g, k - 1, lane);
+    }
 }
 
 __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
@@ -269,59 +348,8 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
         if (lane == 0)
             d = atomicAdd(&J->done, 1u) + 1;
         d = (uint32_t)__builtin_amdgcn_readlane((int)d, 0);
-        if (d == nchunks && lane == 0)
-            finish_level(a, g, level, count);
-    }
-}
-
-// One block per finished graph: follow the creator of each state back through
-// the stored levels (§3.1; the predecessor is found by a block-wide search).
-__global__ void batch_reconstruct_kernel(BatchGraph *graphs, const int32_t *ids, int32_t *orders)
-{
-    __shared__ unsigned long long found;
-    __shared__ uint64_t S_sh, SL_sh;
-    __shared__ uint64_t idx_sh;
-    const int g = ids[blockIdx.x];
-    BatchGraph *G = &graphs[g];
-    int32_t *order = orders + (size_t)blockIdx.x * 64;
-    const int n = G->n;
-    const int L = G->level;
-    if (threadIdx.x == 0) {
-        S_sh = L > 0 ? G->keys[G->level_off[L]] : 0ull;
-        SL_sh = S_sh;
-        idx_sh = 0;
-    }
-    __syncthreads();
-    for (int i = L; i >= 1; --i) {
-        if (threadIdx.x == 0) {
-            const int v = G->lastv[G->level_off[i] + idx_sh];
-            order[i - 1] = v;
-            S_sh &= ~(1ull << v);
-            found = ~0ull;
-        }
-        __syncthreads();
-        if (i > 1) {
-            const uint64_t b = G->level_off[i - 1];
-            const uint64_t e = G->level_off[i];
-            const uint64_t S = S_sh;
-            for (uint64_t t = b + threadIdx.x; t < e; t += blockDim.x)
-                if (G->keys[t] == S)
-                    atomicMin(&found, (unsigned long long)(t - b));
-        }
-        __syncthreads();
-        if (threadIdx.x == 0)
-            idx_sh = found;
-        __syncthreads();
-        if (i > 1 && idx_sh == ~0ull)
-            break;  // cannot happen for a consistent arena; the host width check rejects it
-    }
-    if (threadIdx.x == 0) {
-        int t = L;
-        for (int v = 0; v < n; ++v)
-            if (!((SL_sh >> v) & 1ull))
-                order[t++] = v;
-        for (; t < 64; ++t)
-            order[t] = -1;
+        if (d == nchunks)
+            finish_level(a, g, level, count, lane);
     }
 }
 
@@ -339,15 +367,6 @@ int batch_blocks_per_cu()
 hipError_t launch_batch(const BatchArgs &a, unsigned grid_blocks, hipStream_t s)
 {
     hipLaunchKernelGGL(batch_kernel, dim3(grid_blocks), dim3(kBatchBlock), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_reconstruct(BatchGraph *graphs, const int32_t *ids, int count, int32_t *orders,
-                                    hipStream_t s)
-{
-    if (count <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(batch_reconstruct_kernel, dim3(count), dim3(256), 0, s, graphs, ids, orders);
     return hipGetLastError();
 }
 

@@ -22,8 +22,9 @@ struct LevelArgs {
     void *out;              // level i+1 keys, capacity out_cap
     uint8_t *out_lastv;     // vertex that created each level i+1 key
     uint64_t out_cap;
-    void *table;            // open-addressing table, table_mask+1 slots, all EMPTY on entry
-    uint64_t table_mask;
+    void *table;            // open-addressing table of table_slots entries, all EMPTY on entry
+    uint64_t table_slots;
+    uint64_t allowed;       // vertices that may be added (all for a full search)
     const uint64_t *adj;    // n adjacency rows (device)
     int n;
     int k;

@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
 
         for (int s = 0; s < cnt; ++s) {
             const uint64_t S = read_lane64(mine, s);
-            const bool feas = lane_feasible(S, Aj, lane, a.n, a.k);
+            const bool feas = lane_feasible(S, Aj, lane, a.n, a.k) && ((a.allowed >> lane) & 1ull);
             const uint64_t feas_mask = ballot(feas);
             feasible += (uint64_t)__popcll(feas_mask);
             if (feas_mask == 0ull)
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
                 if (feas)
                     won = bloom_insert(a.bloom, a.bloom_mask, (uint64_t)key);
             } else if (feas) {
-                uint64_t h = slot_hash((uint64_t)key) & a.table_mask;
+                uint64_t h = slot_in((uint64_t)key, a.table_slots);
                 for (uint32_t p = 0;; ++p) {
                     const K old = cas<K>(&table[h], EMPTY, key);
                     if (old == EMPTY) {
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
                         atomicOr(&a.ctr->overflow, 1u);
                         break;
                     }
-                    h = (h + 1) & a.table_mask;
+                    h = h + 1 == a.table_slots ? 0 : h + 1;
                 }
             }
             const uint64_t winners = ballot(won);

@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -57,6 +58,7 @@ struct tw_ctx {
     LevelCounters *h_ctr = nullptr;      // pinned host mirror
     unsigned long long *h_find = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    tw_mpnn *net = nullptr;  // learned start bound (k_policy = TW_K_LEARNED)
 };
 
 namespace {
@@ -269,6 +271,15 @@ struct RunStats {
     uint64_t states_expanded = 0, expansions = 0, successors = 0, unique = 0, peak = 0;
     uint32_t decisions = 0, levels = 0, retries = 0, launches = 0;
     double kernel_seconds = 0;
+    uint64_t run_peak = 0;  // largest level of the last decide run
+};
+
+// Per-graph outcome of a search (start bound, certifying run's peak, work).
+struct GraphOutcome {
+    uint64_t peak_yes = 0, expansions = 0, states = 0;
+    int32_t start_k = 0;
+    uint32_t decisions = 0;
+    int32_t path = 1;
 };
 
 void add_stats(tw_stats *st, const RunStats &r, double secs)
@@ -329,9 +340,12 @@ tw_status emit_level(tw_ctx *c, const Sink &sink, int k, int i, const Level &lv,
 
 // Runs decide(k).  With keep_levels, levels[0..L] stay on the device (each
 // trimmed to its exact size) for order reconstruction; otherwise only the
-// current pair is held.
+// current pair is held and levels.back() is the last level reached.  With
+// allowed != all, only vertices of `allowed` are ever added: the levels are
+// then the full levels restricted to subsets of `allowed` (feasibility of a
+// set does not depend on the vertices outside it being allowed).
 tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const Sink *sink,
-                     std::vector<Level> &levels, int *yes, RunStats &rs)
+                     std::vector<Level> &levels, int *yes, RunStats &rs, uint64_t allowed = ~0ull)
 {
     const int n = g.n;
     const int L = std::max(0, n - k - 1);
@@ -367,6 +381,7 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
     Buf scratch_keys, scratch_lastv;
     tw_status status = TW_OK;
     uint64_t cur = 1;
+    uint64_t run_peak = 1;
     int i = 0;
 
     for (; i < L; ++i) {
@@ -378,24 +393,23 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
         // may both report it new
         const uint64_t pairs = in_count > UINT64_MAX / 64 ? UINT64_MAX : in_count * (uint64_t)(n - i);
         const uint64_t bound = bloom ? pairs : std::min<uint64_t>(binom_sat(n, i + 1), pairs);
+        // first guess of |level i+1|: the last growth ratio with 30% slack
         uint64_t guess;
         if (c->opt.capacity_override)
             guess = c->opt.capacity_override;
         else
-            guess = (uint64_t)std::min<double>((double)in_count * std::max(1.0, growth) * 2.0 + 1024.0,
+            guess = (uint64_t)std::min<double>((double)in_count * std::max(1.0, growth) * 1.3 + 4096.0,
                                                1.8e19);
-        guess = std::min(guess, bound);
-        if (guess < 1)
-            guess = 1;
+        guess = std::max<uint64_t>(std::min(guess, bound), 1);
+        float a_eff = alpha;
 
         uint64_t out_count = 0, succ = 0;
         for (;;) {
             if (c->opt.max_states && guess > c->opt.max_states)
                 guess = std::max<uint64_t>(c->opt.max_states, 1);
-            uint64_t slots = pow2_at_least((uint64_t)((double)guess / alpha) + 1);
-            uint64_t out_cap = std::min<uint64_t>(bound, (uint64_t)((double)slots * 0.85));
-            if (out_cap < guess)
-                out_cap = guess;
+            // table of any size (multiply-shift slot mapping), a multiple of 64 slots
+            uint64_t slots = ((uint64_t)((double)guess / a_eff) + 64 + 63) / 64 * 64;
+            uint64_t out_cap = std::min<uint64_t>(bound, std::max<uint64_t>(guess, (uint64_t)(0.6 * (double)slots)));
             if (c->opt.max_states)
                 out_cap = std::min<uint64_t>(out_cap, c->opt.max_states);
             uint64_t bloom_bits = 0;
@@ -409,6 +423,17 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
                 status = acquire(c, scratch_keys, out_cap * kb);
             if (status == TW_OK)
                 status = acquire(c, scratch_lastv, out_cap);
+            if (status == TW_ENOMEM && !bloom && a_eff < 0.8f) {
+                // short of memory: a fuller table before giving up
+                release(c, scratch_keys);
+                release(c, scratch_lastv);
+                release(c, c->table);
+                drop_cache(c);
+                a_eff = 0.8f;
+                status = TW_OK;
+                c->err.clear();
+                continue;
+            }
             if (status != TW_OK)
                 goto done;
 
@@ -424,7 +449,8 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
             a.out_lastv = (uint8_t *)scratch_lastv.p;
             a.out_cap = out_cap;
             a.table = bloom ? nullptr : c->table.p;
-            a.table_mask = slots - 1;
+            a.table_slots = slots;
+            a.allowed = allowed;
             a.bloom = bloom ? (uint32_t *)c->bloom.p : nullptr;
             a.bloom_mask = bloom ? bloom_bits - 1 : 0;
             a.adj = (const uint64_t *)c->d_adj.p;
@@ -456,18 +482,18 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
                 succ = h.successors;
                 break;
             }
-            // overflow: regrow and replay the level
+            // overflow: regrow and replay the level (h.out_count is a lower bound)
             rs.retries++;
             if (c->opt.max_states && out_cap >= c->opt.max_states) {
                 status = fail(c, TW_ECAPACITY, "level %d needs more than max_states=%llu states",
                               i + 1, (unsigned long long)c->opt.max_states);
                 goto done;
             }
-            if (!bloom && out_cap >= bound && slots >= 2 * bound + 64) {
+            if (!bloom && out_cap >= bound && (double)slots * 0.8 >= (double)bound) {
                 status = fail(c, TW_EDEVICE, "overflow at level %d with capacity at its bound", i + 1);
                 goto done;
             }
-            guess = std::min<uint64_t>(bound, std::max<uint64_t>(guess * 4, h.out_count * 2));
+            guess = std::min<uint64_t>(bound, std::max<uint64_t>(guess * 2, (uint64_t)(1.3 * (double)h.out_count)));
         }
 
         rs.states_expanded += in_count;
@@ -476,6 +502,7 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
         rs.unique += out_count;
         rs.levels++;
         rs.peak = std::max(rs.peak, std::max(out_count, in_count));
+        run_peak = std::max(run_peak, out_count);
         growth = in_count ? (double)out_count / (double)in_count : 1.0;
 
         // the new level: an exact-size copy when levels are kept, else the scratch pair itself
@@ -530,6 +557,7 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
 done:
     release(c, scratch_keys);
     release(c, scratch_lastv);
+    rs.run_peak = run_peak;
     if (status != TW_OK)
         return status;
     *yes = (i >= L && cur > 0) ? 1 : 0;
@@ -610,58 +638,116 @@ void free_levels(tw_ctx *c, std::vector<Level> &levels)
     levels.clear();
 }
 
-tw_status solve_one(tw_ctx *c, const Graph &g, int32_t *out_tw, int32_t *out_order, RunStats &rs)
+// Search from bound k0 (lb <= k0 <= n-1): after a YES at k (its order kept)
+// move down, after a NO move up, until a YES at t meets a NO at t-1 or t = lb.
+// With k0 = lb this is the ascending search of Listing 1 started at the
+// minor-min-width bound.
+tw_status solve_one(tw_ctx *c, const Graph &g, int lb, int k0, int32_t *out_tw, int32_t *out_order,
+                    RunStats &rs, GraphOutcome *oc)
 {
+    const int n = g.n;
+    const uint64_t e0 = rs.expansions, s0 = rs.states_expanded;
+    const uint32_t d0 = rs.decisions;
+    int known_no = lb - 1;
+    int best_yes = n - 1;
+    uint64_t peak_yes = 1;
+    for (int v = 0; v < n; ++v)
+        out_order[v] = v;  // any order has width <= n - 1
+    int k = std::min(std::max(k0, lb), n - 1);
+    if (oc)
+        oc->start_k = k;
+    std::vector<int32_t> order((size_t)n);
     std::vector<Level> levels;
-    const int lb = mmw_bound(g);
-    for (int k = lb; k < g.n; ++k) {
+    while (best_yes > known_no + 1) {
         int yes = 0;
-        tw_status s = run_decide(c, g, k, true, nullptr, levels, &yes, rs);
+        tw_status s = run_decide(c, g, k, false, nullptr, levels, &yes, rs);
         if (s != TW_OK) {
             free_levels(c, levels);
             return s;
         }
         if (yes) {
-            s = reconstruct(c, g, k, levels, out_order);
+            const uint64_t peak = rs.run_peak;
+            // the order: pick one state S_L of the last level and search again
+            // over subsets of S_L only (small), keeping those levels
+            uint64_t SL = 0;
+            const int L = std::max(0, n - k - 1);
+            if (L > 0) {
+                const int kb = n <= 32 ? 4 : 8;
+                HIP_TRY(c, hipMemcpyAsync(&SL, levels.back().keys.p, kb, hipMemcpyDeviceToHost, c->stream));
+                HIP_TRY(c, hipStreamSynchronize(c->stream));
+                free_levels(c, levels);
+                int yes2 = 0;
+                const int dedup = c->opt.dedup;
+                c->opt.dedup = TW_DEDUP_EXACT;  // the small restricted search is always exact
+                s = run_decide(c, g, k, true, nullptr, levels, &yes2, rs, SL);
+                c->opt.dedup = dedup;
+                if (s == TW_OK && !yes2)
+                    s = fail(c, TW_EDEVICE, "restricted search lost the state it started from");
+                if (s != TW_OK) {
+                    free_levels(c, levels);
+                    return s;
+                }
+            }
+            s = reconstruct(c, g, k, levels, order.data());
             free_levels(c, levels);
+            rs.run_peak = peak;
             if (s != TW_OK)
                 return s;
-            const int w = fill_in_width(g, out_order);
-            if (c->opt.dedup == TW_DEDUP_BLOOM && w >= lb && w <= k) {
-                // a Bloom NO below k is not certified; the order itself proves tw <= w
-                *out_tw = w;
-                return TW_OK;
-            }
-            if (w != k)
-                return fail(c, TW_EDEVICE, "order width %d differs from treewidth %d", w, k);
-            *out_tw = k;
-            return TW_OK;
+            const int w = fill_in_width(g, order.data());
+            best_yes = (c->opt.dedup == TW_DEDUP_BLOOM && w >= lb && w < k) ? w : k;
+            peak_yes = rs.run_peak;
+            std::copy(order.begin(), order.end(), out_order);
+            k = best_yes - 1;
+        } else {
+            free_levels(c, levels);
+            known_no = std::max(known_no, k);
+            k = known_no + 1;
         }
+        if (k >= best_yes || k <= known_no)
+            break;
     }
-    free_levels(c, levels);
-    return fail(c, TW_EDEVICE, "no bound k < n was accepted");
+    const int w = fill_in_width(g, out_order);
+    if (w != best_yes)
+        return fail(c, TW_EDEVICE, "order width %d differs from treewidth %d", w, best_yes);
+    *out_tw = best_yes;
+    if (oc) {
+        oc->peak_yes = peak_yes;
+        oc->expansions = rs.expansions - e0;
+        oc->states = rs.states_expanded - s0;
+        oc->decisions = rs.decisions - d0;
+        oc->path = 1;
+    }
+    return TW_OK;
 }
 
-// Runs the persistent batch kernel over batch_ids.  Graphs that finish get
-// their tw and order; graphs whose arena or table filled up are appended to
-// single_ids for the tw_solve path.
-tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<int> &lbs,
-                    const std::vector<int> &ids, int32_t *out_tw, int32_t *out_orders,
-                    const std::vector<size_t> &offs, tw_status *out_status,
-                    std::vector<int> &single_ids, RunStats &rs)
+// One persistent launch over the graphs ids[0..B): start bound k0s[t] and
+// arena of arena[t] states for graph ids[t].  Graphs that finish get their
+// tw, order and outcome; graphs whose arena or table filled up are appended
+// to single_ids for the tw_solve path.
+tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<int> &lbs,
+                       const std::vector<int> &k0s, const std::vector<uint64_t> &arenas,
+                       const std::vector<int> &ids, int32_t *out_tw, int32_t *out_orders,
+                       const std::vector<size_t> &offs, tw_status *out_status, std::vector<int> &single_ids,
+                       std::vector<GraphOutcome> &outcomes, RunStats &rs)
 {
-    if (ids.empty())
-        return TW_OK;
     const size_t B = ids.size();
-    const uint64_t arena = c->opt.batch_graph_states ? c->opt.batch_graph_states : (1ull << 20);
-    const uint64_t slots = pow2_at_least(arena);
+    if (!B)
+        return TW_OK;
     uint32_t chunk = c->opt.batch_chunk ? c->opt.batch_chunk : 256u;
     chunk = std::max<uint32_t>(64u, (chunk + 63u) / 64u * 64u);
-    uint64_t job_cap = 0;
-    for (int t : ids)
-        job_cap += (uint64_t)graphs[(size_t)t].n * (uint64_t)graphs[(size_t)t].n + 1;
-
-    Buf d_graphs, d_jobs, d_q, d_keys, d_lastv, d_table, d_ids, d_orders;
+    uint64_t job_cap = 0, arena_total = 0, slot_total = 0;
+    std::vector<uint64_t> aoff(B), soff(B), slots(B);
+    for (size_t b = 0; b < B; ++b) {
+        const int n = graphs[(size_t)ids[b]].n;
+        job_cap += (uint64_t)n * (uint64_t)n + 1;
+        aoff[b] = arena_total;
+        arena_total += arenas[b];
+        slots[b] = pow2_at_least(arenas[b]);
+        soff[b] = slot_total;
+        slot_total += slots[b];
+    }
+    const size_t job_bytes = (job_cap * sizeof(twk::BatchJob) + 15) / 16 * 16;
+    Buf d_graphs, d_jobs, d_q, d_keys, d_lastv, d_table;
     auto cleanup = [&]() {
         release(c, d_graphs);
         release(c, d_jobs);
@@ -669,25 +755,18 @@ tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vect
         release(c, d_keys);
         release(c, d_lastv);
         release(c, d_table);
-        release(c, d_ids);
-        release(c, d_orders);
     };
     tw_status s = acquire(c, d_graphs, B * sizeof(twk::BatchGraph));
-    const size_t job_bytes = (job_cap * sizeof(twk::BatchJob) + 15) / 16 * 16;
     if (s == TW_OK)
         s = acquire(c, d_jobs, job_bytes);
     if (s == TW_OK)
         s = acquire(c, d_q, sizeof(twk::BatchQueue));
     if (s == TW_OK)
-        s = acquire(c, d_keys, B * arena * sizeof(uint64_t));
+        s = acquire(c, d_keys, arena_total * sizeof(uint64_t));
     if (s == TW_OK)
-        s = acquire(c, d_lastv, B * arena);
+        s = acquire(c, d_lastv, arena_total);
     if (s == TW_OK)
-        s = acquire(c, d_table, B * slots * sizeof(uint64_t));
-    if (s == TW_OK)
-        s = acquire(c, d_ids, B * sizeof(int32_t));
-    if (s == TW_OK)
-        s = acquire(c, d_orders, B * 64 * sizeof(int32_t));
+        s = acquire(c, d_table, slot_total * sizeof(uint64_t));
     if (s != TW_OK) {
         cleanup();
         return s;
@@ -695,43 +774,46 @@ tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vect
     std::vector<twk::BatchGraph> hg(B);
     std::vector<twk::BatchJob> hj(B);
     for (size_t b = 0; b < B; ++b) {
-        const Graph &g = graphs[(size_t)ids[b]];
+        const int t = ids[b];
+        const Graph &g = graphs[(size_t)t];
         twk::BatchGraph &G = hg[b];
         std::memset(&G, 0, sizeof G);
         for (int j = 0; j < g.n; ++j)
             G.adj[j] = g.rows[j];
-        G.keys = (uint64_t *)d_keys.p + b * arena;
-        G.lastv = (uint8_t *)d_lastv.p + b * arena;
-        G.arena_cap = arena;
-        G.table = (uint64_t *)d_table.p + b * slots;
-        G.table_mask = slots - 1;
+        G.keys = (uint64_t *)d_keys.p + aoff[b];
+        G.lastv = (uint8_t *)d_lastv.p + aoff[b];
+        G.arena_cap = arenas[b];
+        G.table = (uint64_t *)d_table.p + soff[b];
+        G.table_mask = slots[b] - 1;
         G.level_off[0] = 0;
         G.level_off[1] = 1;
         G.status = twk::kBatchRunning;
         G.n = g.n;
-        G.k = lbs[(size_t)ids[b]];
+        G.k = k0s[(size_t)t];
         G.level = 0;
         G.L = g.n - G.k - 1;
         G.tw = -1;
+        G.known_no = lbs[(size_t)t] - 1;
+        G.best_yes = g.n - 1;
         G.tag = 1;
         G.decisions = 1;
+        G.peak_k = 1;
+        G.peak_yes = 1;
+        for (int v = 0; v < 64; ++v)
+            G.order[v] = v < g.n ? v : -1;
         twk::BatchJob &J = hj[b];
         std::memset(&J, 0, sizeof J);
         J.graph = (int32_t)b;
-        J.level = 0;
-        J.begin = 0;
         J.count = 1;
         J.nchunks = 1;
         J.ready = 1;
     }
     twk::BatchQueue hq{};
-    hq.head = 0;
     hq.tail = B;
     hq.capacity = job_cap;
     hq.active = (uint32_t)B;
-    hq.abort = 0;
     // tables start with tag 0 (never a live tag); jobs beyond the first B are not ready
-    HIP_TRY(c, twk::launch_fill_zero(d_table.p, B * slots * sizeof(uint64_t), c->stream));
+    HIP_TRY(c, twk::launch_fill_zero(d_table.p, slot_total * sizeof(uint64_t), c->stream));
     HIP_TRY(c, twk::launch_fill_zero(d_jobs.p, job_bytes, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d_graphs.p, hg.data(), B * sizeof(twk::BatchGraph), hipMemcpyHostToDevice,
                               c->stream));
@@ -763,52 +845,128 @@ tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vect
         HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
         rs.kernel_seconds += ms * 1e-3;
     }
-    if (hq.abort) {
-        cleanup();
+    cleanup();
+    if (hq.abort)
         return fail(c, TW_EDEVICE, "batch kernel aborted (work-queue wait bound or job capacity)");
-    }
-    std::vector<int32_t> done_local;
     for (size_t b = 0; b < B; ++b) {
         const twk::BatchGraph &G = hg[b];
+        const int t = ids[b];
         rs.states_expanded += G.states;
         rs.expansions += G.expansions;
         rs.successors += G.successors;
         rs.levels += G.levels_run;
         rs.decisions += G.decisions;
-        rs.peak = std::max<uint64_t>(rs.peak, G.peak);
         rs.unique += G.unique;
-        if (G.status == twk::kBatchDone)
-            done_local.push_back((int32_t)b);
-        else
-            single_ids.push_back(ids[b]);
+        rs.peak = std::max<uint64_t>(rs.peak, G.peak);
+        if (G.status != twk::kBatchDone) {
+            single_ids.push_back(t);
+            continue;
+        }
+        const Graph &g = graphs[(size_t)t];
+        int32_t *o = out_orders + offs[(size_t)t];
+        for (int v = 0; v < g.n; ++v)
+            o[v] = G.order[v];
+        const int w = fill_in_width(g, o);
+        if (w != G.tw) {
+            out_status[t] = fail(c, TW_EDEVICE, "batch graph %d: order width %d != treewidth %d", t, w, G.tw);
+            continue;
+        }
+        out_tw[t] = G.tw;
+        out_status[t] = TW_OK;
+        GraphOutcome &oc = outcomes[(size_t)t];
+        oc.peak_yes = G.peak_yes;
+        oc.expansions = G.expansions;
+        oc.states = G.states;
+        oc.start_k = k0s[(size_t)t];
+        oc.decisions = G.decisions;
+        oc.path = 0;
     }
-    if (!done_local.empty()) {
-        HIP_TRY(c, hipMemcpyAsync(d_ids.p, done_local.data(), done_local.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(c, twk::launch_batch_reconstruct((twk::BatchGraph *)d_graphs.p, (const int32_t *)d_ids.p,
-                                                 (int)done_local.size(), (int32_t *)d_orders.p, c->stream));
-        std::vector<int32_t> orders(done_local.size() * 64);
-        HIP_TRY(c, hipMemcpyAsync(orders.data(), d_orders.p, orders.size() * sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        for (size_t q = 0; q < done_local.size(); ++q) {
-            const int b = done_local[q];
-            const int t = ids[(size_t)b];
-            const Graph &g = graphs[(size_t)t];
-            int32_t *o = out_orders + offs[(size_t)t];
-            for (int v = 0; v < g.n; ++v)
-                o[v] = orders[q * 64 + (size_t)v];
-            const int w = fill_in_width(g, o);
-            if (w != hg[(size_t)b].tw) {
-                out_status[t] = fail(c, TW_EDEVICE, "batch graph %d: order width %d != treewidth %d", t, w,
-                                     hg[(size_t)b].tw);
-                continue;
-            }
-            out_tw[t] = hg[(size_t)b].tw;
-            out_status[t] = TW_OK;
+    return TW_OK;
+}
+
+// Splits the batchable graphs into launches that fit a device-memory budget.
+tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<int> &lbs,
+                    const std::vector<int> &k0s, const std::vector<uint64_t> &arena_of,
+                    const std::vector<int> &ids, int32_t *out_tw, int32_t *out_orders,
+                    const std::vector<size_t> &offs, tw_status *out_status, std::vector<int> &single_ids,
+                    std::vector<GraphOutcome> &outcomes, RunStats &rs)
+{
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
+        free_b = (size_t)32 << 30;
+    const uint64_t budget = std::max<uint64_t>((uint64_t)(free_b / 2), (uint64_t)1 << 30);
+    std::vector<int> group;
+    std::vector<uint64_t> arenas;
+    uint64_t used = 0;
+    for (size_t q = 0; q <= ids.size(); ++q) {
+        uint64_t need = 0;
+        if (q < ids.size())
+            need = arena_of[(size_t)ids[q]] * 9 + pow2_at_least(arena_of[(size_t)ids[q]]) * 8 + 4096;
+        if (q == ids.size() || (!group.empty() && used + need > budget)) {
+            tw_status s = batch_launch(c, graphs, lbs, k0s, arenas, group, out_tw, out_orders, offs, out_status,
+                                       single_ids, outcomes, rs);
+            if (s != TW_OK)
+                return s;
+            group.clear();
+            arenas.clear();
+            used = 0;
+        }
+        if (q < ids.size()) {
+            group.push_back(ids[q]);
+            arenas.push_back(arena_of[(size_t)ids[q]]);
+            used += need;
         }
     }
-    cleanup();
+    return TW_OK;
+}
+
+bool read_weights(const char *path, std::vector<float> &params)
+{
+    if (!path)
+        return false;
+    FILE *f = std::fopen(path, "rb");
+    if (!f)
+        return false;
+    char magic[8];
+    uint32_t count = 0;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "TWMPNN01", 8) == 0 &&
+              std::fread(&count, 4, 1, f) == 1 && count == tw_mpnn_param_count();
+    if (ok) {
+        params.resize(count);
+        ok = std::fread(params.data(), 4, count, f) == count;
+    }
+    std::fclose(f);
+    return ok;
+}
+
+// Learned start bounds and arena sizes for graphs ids (network outputs: tw/n
+// and log2(peak + 1)/32).  The start bound is the prediction rounded down
+// (a NO below tw costs less than a YES above it), clamped to [lb, n-2].
+tw_status predict_starts(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<int> &lbs,
+                         const std::vector<int> &ids, std::vector<int> &k0s, std::vector<uint64_t> &arena_of)
+{
+    if (!c->net || ids.empty())
+        return TW_OK;
+    std::vector<tw_graph> gs(ids.size());
+    for (size_t q = 0; q < ids.size(); ++q) {
+        gs[q].n = (uint32_t)graphs[(size_t)ids[q]].n;
+        gs[q].adj = graphs[(size_t)ids[q]].rows;
+    }
+    std::vector<float> pred(ids.size() * 2);
+    tw_status s = tw_mpnn_predict(c->net, gs.data(), (uint32_t)ids.size(), pred.data());
+    if (s != TW_OK)
+        return fail(c, s, "network prediction failed");
+    for (size_t q = 0; q < ids.size(); ++q) {
+        const int t = ids[q];
+        const int n = graphs[(size_t)t].n;
+        const double tw_pred = (double)pred[2 * q] * n;
+        int k0 = (int)std::floor(tw_pred);
+        k0 = std::max(lbs[(size_t)t], std::min(k0, n - 2));
+        k0s[(size_t)t] = k0;
+        const double peak = std::exp2(std::min(40.0, std::max(0.0, 32.0 * (double)pred[2 * q + 1]))) - 1.0;
+        const uint64_t want = (uint64_t)std::max(4096.0, std::min(16.0 * peak, (double)(1ull << 22)));
+        arena_of[(size_t)t] = pow2_at_least(want);
+    }
     return TW_OK;
 }
 
@@ -886,6 +1044,17 @@ tw_status tw_ctx_create(const tw_options *options, tw_ctx **out)
         tw_ctx_destroy(c);
         return TW_ENOMEM;
     }
+    if (c->opt.k_policy == TW_K_LEARNED) {
+        std::vector<float> params;
+        if (!read_weights(c->opt.weights_path, params) ||
+            tw_mpnn_create(c->device, c->stream, params.data(), &c->net) != TW_OK) {
+            tw_ctx_destroy(c);
+            return TW_EINVAL;
+        }
+    } else if (c->opt.k_policy != TW_K_ASCENDING) {
+        tw_ctx_destroy(c);
+        return TW_EINVAL;
+    }
     *out = c;
     return TW_OK;
 }
@@ -895,6 +1064,8 @@ void tw_ctx_destroy(tw_ctx *c)
     if (!c)
         return;
     (void)hipSetDevice(c->device);
+    if (c->net)
+        tw_mpnn_destroy(c->net);
     if (c->stream)
         (void)hipStreamSynchronize(c->stream);
     release(c, c->d_adj);
@@ -984,7 +1155,16 @@ tw_status tw_solve(tw_ctx *c, const tw_graph *gr, int32_t *out_tw, int32_t *out_
         return fail(c, TW_EDEVICE, "hipSetDevice failed");
     const double t0 = now_s();
     RunStats rs;
-    s = solve_one(c, g, out_tw, out_order, rs);
+    const int lb = mmw_bound(g);
+    std::vector<Graph> one(1, g);
+    std::vector<int> lbs(1, lb), k0s(1, lb), ids(1, 0);
+    std::vector<uint64_t> arena(1, 0);
+    if (lb < g.n - 1) {
+        s = predict_starts(c, one, lbs, ids, k0s, arena);
+        if (s != TW_OK)
+            return s;
+    }
+    s = solve_one(c, g, lb, k0s[0], out_tw, out_order, rs, nullptr);
     if (s != TW_OK)
         return s;
     add_stats(stats, rs, now_s() - t0);
@@ -992,7 +1172,8 @@ tw_status tw_solve(tw_ctx *c, const tw_graph *gr, int32_t *out_tw, int32_t *out_
 }
 
 tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t *out_tw,
-                         int32_t *out_orders, tw_status *out_status, tw_stats *stats)
+                         int32_t *out_orders, tw_status *out_status, tw_graph_stats *out_graph_stats,
+                         tw_stats *stats)
 {
     if (!c || (count && (!gs || !out_tw || !out_orders || !out_status)))
         return TW_EINVAL;
@@ -1003,9 +1184,12 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
     RunStats rs;
     std::vector<Graph> graphs(count);
     std::vector<size_t> offs(count);
-    std::vector<int> lbs(count, 0);
+    std::vector<int> lbs(count, 0), k0s(count, 0);
+    std::vector<uint64_t> arena_of(count, 0);
+    std::vector<GraphOutcome> outcomes(count);
     std::vector<int> batch_ids;   // graphs that go into the persistent launch
     std::vector<int> single_ids;  // graphs solved one at a time
+    const uint64_t default_arena = c->opt.batch_graph_states ? c->opt.batch_graph_states : (1ull << 20);
     size_t off = 0;
     for (uint32_t t = 0; t < count; ++t) {
         offs[t] = off;
@@ -1015,31 +1199,57 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
         if (out_status[t] != TW_OK)
             continue;
         const Graph &g = graphs[t];
-        lbs[t] = mmw_bound(g);
+        lbs[t] = k0s[t] = mmw_bound(g);
+        // an arena never needs more than every subset of V (minus V itself)
+        arena_of[t] = g.n < 20 ? std::min<uint64_t>(default_arena, 1ull << g.n) : default_arena;
         if (lbs[t] >= g.n - 1) {
             // tw = n - 1: decide(n - 1) needs no level; any order has width n - 1
             out_tw[t] = g.n - 1;
             for (int v = 0; v < g.n; ++v)
                 out_orders[offs[t] + v] = v;
-            rs.decisions++;
+            outcomes[t].start_k = g.n - 1;
+            outcomes[t].path = 2;
         } else if (g.n <= twk::kBatchMaxN && c->opt.dedup == TW_DEDUP_EXACT) {
             batch_ids.push_back((int)t);
         } else {
             single_ids.push_back((int)t);
         }
     }
-    tw_status st = batch_run(c, graphs, lbs, batch_ids, out_tw, out_orders, offs, out_status,
-                             single_ids, rs);
+    std::vector<int> learned_ids = batch_ids;
+    learned_ids.insert(learned_ids.end(), single_ids.begin(), single_ids.end());
+    tw_status st = predict_starts(c, graphs, lbs, learned_ids, k0s, arena_of);
+    if (st != TW_OK)
+        return st;
+    if (c->opt.batch_graph_states)
+        for (int t : batch_ids)
+            arena_of[(size_t)t] = c->opt.batch_graph_states;
+    st = batch_run(c, graphs, lbs, k0s, arena_of, batch_ids, out_tw, out_orders, offs, out_status, single_ids,
+                   outcomes, rs);
     if (st != TW_OK)
         return st;
     for (int t : single_ids) {
-        tw_status s = solve_one(c, graphs[(size_t)t], &out_tw[t], out_orders + offs[(size_t)t], rs);
+        GraphOutcome oc;
+        tw_status s = solve_one(c, graphs[(size_t)t], lbs[(size_t)t], k0s[(size_t)t], &out_tw[t],
+                                out_orders + offs[(size_t)t], rs, &oc);
         out_status[t] = s;
         if (s != TW_OK)
             out_tw[t] = -1;
+        else
+            outcomes[(size_t)t] = oc;
         if (s == TW_EDEVICE)
             return s;
     }
+    if (out_graph_stats)
+        for (uint32_t t = 0; t < count; ++t) {
+            tw_graph_stats &o = out_graph_stats[t];
+            std::memset(&o, 0, sizeof o);
+            o.peak_yes = outcomes[t].peak_yes;
+            o.expansions = outcomes[t].expansions;
+            o.states_expanded = outcomes[t].states;
+            o.start_k = outcomes[t].start_k;
+            o.decisions = outcomes[t].decisions;
+            o.path = outcomes[t].path;
+        }
     add_stats(stats, rs, now_s() - t0);
     return TW_OK;
 }

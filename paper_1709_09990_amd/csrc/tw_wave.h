@@ -49,31 +49,42 @@ __device__ __forceinline__ uint64_t slot_hash(uint64_t key)
     return h;
 }
 
-// |Q(S, v)| <= k for this lane's vertex v (§2): components of G[S] by ballot
-// breadth-first search; N_out(K) of each component by one more ballot; lane v
-// unions N_out(K) for the components it touches.  Aj is this lane's adjacency
-// row (0 for lanes >= n).  Returns whether lane v is a feasible successor.
+// |Q(S, v)| <= k for this lane's vertex v (§2).  Components of G[S] by ballot
+// breadth-first search: lane j reports whether its row A[j] meets the current
+// set; the lanes of S among them extend the component, and once it stops
+// growing the lanes outside S among them are N_out(K), the outside vertices
+// adjacent to K.  Lane v unions N_out(K) for the components it touches.  Aj is
+// this lane's adjacency row (0 for lanes >= n).  Returns whether lane v is a
+// feasible successor.
 __device__ __forceinline__ bool lane_feasible(uint64_t S, uint64_t Aj, int lane, int n, int k)
 {
     const uint64_t lanebit = 1ull << lane;
-    const bool inS = (S >> lane) & 1ull;
     uint64_t qacc = 0;
     uint64_t rem = S;
     while (rem) {
         uint64_t comp = rem & (~rem + 1ull);
+        uint64_t touch;
         for (;;) {
-            const uint64_t nxt = comp | ballot(inS && (Aj & comp) != 0ull);
+            touch = ballot((Aj & comp) != 0ull);
+            const uint64_t nxt = comp | (touch & S);
             if (nxt == comp)
                 break;
             comp = nxt;
         }
         rem &= ~comp;
-        const uint64_t nout = ballot(!inS && (Aj & comp) != 0ull);
+        const uint64_t nout = touch & ~S;
         if (nout & lanebit)
             qacc |= nout;
     }
     const uint64_t Q = (Aj | qacc) & ~S & ~lanebit;
-    return lane < n && !inS && __popcll(Q) <= k;
+    return lane < n && !((S >> lane) & 1ull) && __popcll(Q) <= k;
+}
+
+// Slot of a key in a table of `slots` entries (any size): the high half of
+// hash * slots (multiply-shift range reduction).
+__device__ __forceinline__ uint64_t slot_in(uint64_t key, uint64_t slots)
+{
+    return __umul64hi(slot_hash(key), slots);
 }
 
 }  // namespace twk

@@ -75,6 +75,18 @@ class _LevelRecord(ctypes.Structure):
     ]
 
 
+class _GraphStats(ctypes.Structure):
+    _fields_ = [
+        ("peak_yes", ctypes.c_uint64),
+        ("expansions", ctypes.c_uint64),
+        ("states_expanded", ctypes.c_uint64),
+        ("start_k", ctypes.c_int32),
+        ("decisions", ctypes.c_uint32),
+        ("path", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
 _SINK = ctypes.CFUNCTYPE(None, ctypes.POINTER(_LevelRecord), ctypes.c_void_p)
 
 # every function declared in include/tw.h
@@ -105,7 +117,7 @@ def load():
     L.tw_decide.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_int32, P(ctypes.c_int32), P(_Stats)]
     L.tw_solve.argtypes = [ctypes.c_void_p, P(_Graph), P(ctypes.c_int32), P(ctypes.c_int32), P(_Stats)]
     L.tw_solve_batch.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_uint32, P(ctypes.c_int32),
-                                 P(ctypes.c_int32), P(ctypes.c_int), P(_Stats)]
+                                 P(ctypes.c_int32), P(ctypes.c_int), P(_GraphStats), P(_Stats)]
     L.tw_trace_decide.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_int32, _SINK, ctypes.c_void_p,
                                   P(ctypes.c_int32)]
     L.tw_mmw.argtypes = [P(_Graph), P(ctypes.c_int32)]
@@ -242,7 +254,8 @@ class Context:
                                      order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(s)))
         return tw.value, order, _stats_dict(s)
 
-    def solve_batch(self, graphs):
+    def solve_batch(self, graphs, graph_stats: bool = False):
+        """tw, orders, statuses, stats (and per-graph stats dicts if asked)."""
         arrs = [np.ascontiguousarray(np.asarray(r, dtype=np.uint64)) for r in graphs]
         gs = (_Graph * max(1, len(arrs)))()
         for t, a in enumerate(arrs):
@@ -253,15 +266,21 @@ class Context:
         orders = np.zeros(max(1, sum(len(a) for a in arrs)), dtype=np.int32)
         status = np.zeros(max(1, cnt), dtype=np.int32)
         s = _Stats()
+        gst = (_GraphStats * max(1, cnt))()
         self._check(self._L.tw_solve_batch(
             self._h, gs, cnt, tws.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
             orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-            status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(s)))
+            status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), gst, ctypes.byref(s)))
         out_orders, off = [], 0
         for a in arrs:
             out_orders.append(orders[off:off + len(a)].copy())
             off += len(a)
-        return tws[:cnt].copy(), out_orders, status[:cnt].copy(), _stats_dict(s)
+        res = (tws[:cnt].copy(), out_orders, status[:cnt].copy(), _stats_dict(s))
+        if graph_stats:
+            per = [{name: getattr(gst[t], name) for name, _ in _GraphStats._fields_ if name != "reserved"}
+                   for t in range(cnt)]
+            return res + (per,)
+        return res
 
     def trace_decide(self, rows, k: int):
         """decide(k) returning every level (states unordered) as Level records."""
@@ -370,3 +389,24 @@ class Mpnn:
                                                t.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                                float(lr), float(weight_decay), ctypes.byref(loss)))
         return loss.value
+
+
+WEIGHTS_MAGIC = b"TWMPNN01"
+
+
+def write_weights(path: str, params) -> None:
+    """Write network parameters in the file format tw_ctx_create reads for
+    the learned start bound: magic, uint32 count, float32 values (little-endian)."""
+    p = np.ascontiguousarray(params, dtype="<f4")
+    with open(path, "wb") as f:
+        f.write(WEIGHTS_MAGIC)
+        f.write(np.uint32(p.size).astype("<u4").tobytes())
+        f.write(p.tobytes())
+
+
+def read_weights(path: str) -> np.ndarray:
+    with open(path, "rb") as f:
+        if f.read(8) != WEIGHTS_MAGIC:
+            raise ValueError("not a network parameter file")
+        count = int(np.frombuffer(f.read(4), dtype="<u4")[0])
+        return np.frombuffer(f.read(4 * count), dtype="<f4").copy()

@@ -315,3 +315,43 @@ def test_batch_fallback_on_small_arena(oracle):
     assert list(tws) == want
     for rows, tw, order in zip(graphs, tws, orders):
         assert oracle.order_width(rows, order) == tw
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_learned_start_is_exact(oracle, tmp_path, seed):
+    """The learned start bound only changes where the search begins: with any
+    network (here an untrained one, so predictions land above and below tw)
+    the batched and single answers equal the oracle's, orders have that width,
+    and the per-graph start bounds differ from the plain lower bounds."""
+    from oracle import mpnn_ref as M
+    from paper_1709_09990_amd import tw as T
+    p = M.flatten(M.init_params(100 + seed)).astype(np.float32)
+    # bias the tw head so the start lands well inside [lb, n-2]
+    p[-2] = 0.45 if seed == 0 else 0.2
+    wpath = str(tmp_path / "w.bin")
+    T.write_weights(wpath, p)
+    graphs = G.workload_batch(40, seed0=34000 + 100 * seed, n_lo=8, n_hi=26)
+    want = [oracle.treewidth_bfs(r, oracle.mmw(r)) for r in graphs]
+    with T.Context(device=0, k_policy=T.TW_K_LEARNED, weights_path=wpath) as c:
+        tws, orders, status, st, per = c.solve_batch(graphs, graph_stats=True)
+        assert list(status) == [0] * len(graphs)
+        assert list(tws) == want
+        for rows, tw, order in zip(graphs, tws, orders):
+            assert oracle.order_width(rows, order) == tw
+        starts = [q["start_k"] for q in per]
+        assert any(s != T.mmw(r) for s, r in zip(starts, graphs))
+        for rows, tw in list(zip(graphs, want))[:8]:
+            got, order, _ = c.solve(rows)
+            assert got == tw and oracle.order_width(rows, order) == tw
+
+
+def test_batch_graph_stats_peak(oracle):
+    """Per-graph peak of the certifying run equals the oracle's largest level
+    of decide(tw)."""
+    from paper_1709_09990_amd import tw as T
+    graphs = G.workload_batch(16, seed0=35000, n_lo=8, n_hi=22)
+    with T.Context(device=0) as c:
+        tws, _, status, _, per = c.solve_batch(graphs, graph_stats=True)
+    for rows, tw, q in zip(graphs, tws, per):
+        _, levels, _ = oracle.decide(rows, int(tw))
+        assert q["peak_yes"] == max(len(f) for f in levels)
