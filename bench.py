@@ -55,6 +55,28 @@ def _workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+PROFILE = os.path.join(ROOT, "profiles", "expand_kernel_single_n40.md")
+KERNEL_SOURCES = ("tw_kernels.hip", "tw_wave.h", "tw_internal.h")
+
+
+def measured_traffic():
+    """HBM bytes per expansion launch from the committed rocprofv3 counter
+    summary, or None if the kernel sources changed since it was taken."""
+    import hashlib
+    if not os.path.exists(PROFILE):
+        return None
+    fields = {}
+    for line in open(PROFILE):
+        if "=" in line and line.startswith("    "):
+            k, v = line.strip().split("=", 1)
+            fields[k.strip()] = v.strip()
+    src = b"".join(open(os.path.join(ROOT, "paper_1709_09990_amd", "csrc", f), "rb").read()
+                   for f in KERNEL_SOURCES)
+    if fields.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def copy_probe(nbytes: int, reps: int = 5):
     """A plain device-to-device copy of known size (read nbytes, write nbytes),
     run only to scale the FETCH_SIZE / WRITE_SIZE counters of a profile."""
@@ -164,7 +186,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 5),
-        "traffic": None,
+        "traffic": measured_traffic(),
         "kernel": "expand_kernel<uint%d>" % (8 * w),
         "launches": total["launches"],
         "avg_launch_us": round(ks / max(1, total["launches"]) * 1e6, 2),

@@ -83,6 +83,8 @@ typedef struct {
     uint64_t capacity_override; /* test hook: first guess of every level's size (0 = estimate); a
                                    small value forces the overflow -> regrow -> replay path */
     int timing;               /* 1: time every expansion launch with HIP events (tw_stats.kernel_*) */
+    int probe;                /* exact table probe: 0 = default, 1 = compare-and-swap only,
+                                 2 = plain load first, CAS only on an empty slot */
     /* tw_solve_batch: graphs with n <= 48 run in one persistent launch, each with
        its own state arena (all levels of its current bound) and hash table. */
     uint64_t batch_graph_states; /* arena states per graph (0 = 2^20); a graph that outgrows its

@@ -26,7 +26,7 @@ struct BatchGraph {
     uint8_t *lastv;
     uint64_t arena_cap;      // states the arena holds
     uint64_t *table;         // tagged open-addressing table (tag << 48 | key), zero-initialised
-    uint64_t table_mask;
+    uint64_t table_slots;
     uint64_t level_off[66];  // arena offset of level i (current bound)
     unsigned long long out_count;   // states claimed for the level being built
     unsigned long long successors;  // feasible pairs over the whole solve

@@ -245,10 +245,10 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
         const int n = (int)first_lane32((uint32_t)G->n);
         const int k = (int)first_lane32((uint32_t)G->k);
         const uint64_t tag = (uint64_t)first_lane32(G->tag) << kBatchKeyBits;
-        const uint64_t tmask = read_lane64(G->table_mask, 0);
+        const uint64_t tslots = read_lane64(G->table_slots, 0);
         const uint64_t out_base = read_lane64(G->level_off[level + 1], 0);
         const uint64_t arena_cap = read_lane64(G->arena_cap, 0);
-        const uint64_t max_fill = (uint64_t)((double)(tmask + 1) * a.max_load);
+        const uint64_t max_fill = (uint64_t)((double)tslots * a.max_load);
         uint64_t *keys = G->keys;
         uint8_t *lastv = G->lastv;
         uint64_t *table = G->table;
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
                 bool won = false;
                 if (feas) {
                     const uint64_t want = tag | key;
-                    uint64_t slot = slot_hash(key) & tmask;
+                    uint64_t slot = slot_in(key, tslots);
                     uint64_t cur = ld_relaxed(&table[slot]);
                     for (uint32_t p = 0;;) {
                         if ((cur & ~kKeyMask) == tag) {
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
                                 overflow = true;
                                 break;
                             }
-                            slot = (slot + 1) & tmask;
+                            slot = slot + 1 == tslots ? 0 : slot + 1;
                             cur = ld_relaxed(&table[slot]);
                             continue;
                         }

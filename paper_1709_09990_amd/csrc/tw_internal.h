@@ -30,6 +30,7 @@ struct LevelArgs {
     int k;
     LevelCounters *ctr;
     uint32_t max_probe;     // probe-length backstop
+    int read_first;         // 1: plain load before the compare-and-swap (slots only go EMPTY -> key)
     int key_bytes;          // 4 (n <= 32) or 8
     // Bloom-filter variant (§3.2): used instead of the table when bloom != nullptr
     uint32_t *bloom;        // bit array of bloom_mask+1 bits, all zero on entry

@@ -167,10 +167,17 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
             } else if (feas) {
                 uint64_t h = slot_in((uint64_t)key, a.table_slots);
                 for (uint32_t p = 0;; ++p) {
-                    const K old = cas<K>(&table[h], EMPTY, key);
+                    // Within a level a slot only ever goes from EMPTY to a key,
+                    // so a loaded key is final: only an EMPTY slot needs the CAS.
+                    K old = EMPTY;
+                    if (a.read_first)
+                        old = __hip_atomic_load(&table[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (old == EMPTY) {
-                        won = true;
-                        break;
+                        old = cas<K>(&table[h], EMPTY, key);
+                        if (old == EMPTY) {
+                            won = true;
+                            break;
+                        }
                     }
                     if (old == key)
                         break;

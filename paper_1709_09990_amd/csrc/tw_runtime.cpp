@@ -458,6 +458,7 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
             a.k = k;
             a.ctr = (LevelCounters *)c->d_ctr.p;
             a.max_probe = (uint32_t)std::min<uint64_t>(slots, 1u << 16);
+            a.read_first = c->opt.probe == 1 ? 0 : 1;
             a.key_bytes = kb;
             const uint64_t waves = (in_count + 63) / 64;
             uint64_t blocks = (waves + twk::kWavesPerBlock - 1) / twk::kWavesPerBlock;
@@ -735,6 +736,7 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
         return TW_OK;
     uint32_t chunk = c->opt.batch_chunk ? c->opt.batch_chunk : 256u;
     chunk = std::max<uint32_t>(64u, (chunk + 63u) / 64u * 64u);
+    const float alpha = (c->opt.load_factor > 0.f && c->opt.load_factor <= 0.9f) ? c->opt.load_factor : 0.5f;
     uint64_t job_cap = 0, arena_total = 0, slot_total = 0;
     std::vector<uint64_t> aoff(B), soff(B), slots(B);
     for (size_t b = 0; b < B; ++b) {
@@ -742,7 +744,8 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
         job_cap += (uint64_t)n * (uint64_t)n + 1;
         aoff[b] = arena_total;
         arena_total += arenas[b];
-        slots[b] = pow2_at_least(arenas[b]);
+        // table sized for the arena at the target load (a level holds well under the whole arena)
+        slots[b] = ((uint64_t)((double)arenas[b] * 0.5 / alpha) + 64 + 63) / 64 * 64;
         soff[b] = slot_total;
         slot_total += slots[b];
     }
@@ -784,7 +787,7 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
         G.lastv = (uint8_t *)d_lastv.p + aoff[b];
         G.arena_cap = arenas[b];
         G.table = (uint64_t *)d_table.p + soff[b];
-        G.table_mask = slots[b] - 1;
+        G.table_slots = slots[b];
         G.level_off[0] = 0;
         G.level_off[1] = 1;
         G.status = twk::kBatchRunning;
@@ -827,7 +830,7 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
     a.q = (twk::BatchQueue *)d_q.p;
     a.chunk = chunk;
     a.max_probe = 1u << 14;
-    a.max_load = 0.7f;
+    a.max_load = 0.85f;
     a.spin_limit = 20u * 1000u * 1000u;
     const unsigned grid = (unsigned)(c->cu_count * twk::batch_blocks_per_cu());
     if (c->opt.timing)
@@ -901,7 +904,7 @@ tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vect
     for (size_t q = 0; q <= ids.size(); ++q) {
         uint64_t need = 0;
         if (q < ids.size())
-            need = arena_of[(size_t)ids[q]] * 9 + pow2_at_least(arena_of[(size_t)ids[q]]) * 8 + 4096;
+            need = arena_of[(size_t)ids[q]] * 9 + arena_of[(size_t)ids[q]] * 8 + 4096;
         if (q == ids.size() || (!group.empty() && used + need > budget)) {
             tw_status s = batch_launch(c, graphs, lbs, k0s, arenas, group, out_tw, out_orders, offs, out_status,
                                        single_ids, outcomes, rs);
