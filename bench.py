@@ -11,6 +11,9 @@ solves and nothing else.
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
 
 Prints one JSON line.  Fields beyond the driver's contract:
+  batch         graphs solved per second on 512 held-out graphs (n 20..32),
+                batched, plain ascending-k vs the learned start bound
+                (outside the timed region of `value`)
   roofline      the expansion kernel against HBM bandwidth, algorithmic bytes
                 (key read per state, one compare-and-swap per feasible pair,
                 key + creator byte written per new state) over the kernel time
@@ -89,6 +92,37 @@ def copy_probe(nbytes: int, reps: int = 5):
     print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
 
 
+WEIGHTS = os.path.join(ROOT, "paper_1709_09990_amd", "weights", "mpnn_mixture_n16_30.bin")
+
+
+def batch_leg(count: int = 512):
+    """Graphs solved per second, batched: plain ascending-k search vs the
+    learned start bound and admission, on held-out graphs of the uneven
+    mixture (n 20..32, seeds 600000+), same GPU, identical answers required."""
+    from paper_1709_09990_amd import graphs as G
+    from paper_1709_09990_amd import tw as T
+    import numpy as np
+    graphs = G.workload_batch(count, seed0=600000, n_lo=20, n_hi=32)
+    out = {"graphs": count, "n": [20, 32], "weights": os.path.relpath(WEIGHTS, ROOT)}
+    ref = None
+    for name, kw in (("plain", {}), ("learned", {"k_policy": T.TW_K_LEARNED, "weights_path": WEIGHTS})):
+        with T.Context(device=0, **kw) as c:
+            c.solve_batch(graphs[:16])
+            t0 = time.perf_counter()
+            tws, _, status, st = c.solve_batch(graphs)
+            dt = time.perf_counter() - t0
+        if np.any(status != 0):
+            raise RuntimeError(f"batch leg: {name} failed on {int(np.sum(status != 0))} graphs")
+        ref = tws if ref is None else ref
+        out[f"{name}_graphs_per_s"] = round(count / dt, 2)
+        out[f"{name}_expansions"] = st["expansions"]
+        out[f"{name}_bounds_tried"] = st["decisions"]
+        if name == "learned":
+            out["identical"] = bool(np.array_equal(ref, tws))
+    out["learned_speedup"] = round(out["learned_graphs_per_s"] / out["plain_graphs_per_s"], 3)
+    return out
+
+
 def cpu_baseline(budget_s: float = 15.0):
     """The oracle timed on a bounded prefix: levels of decide(8) on the random
     partial 8-tree (n=40) until the budget is spent."""
@@ -132,6 +166,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched learned-vs-plain leg")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -217,6 +252,8 @@ def main():
         "roofline": roofline,
     }
     ctx.close()
+    if not args.no_batch:
+        out["batch"] = batch_leg()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     print(json.dumps(out), flush=True)

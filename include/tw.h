@@ -87,8 +87,9 @@ typedef struct {
                                  2 = plain load first, CAS only on an empty slot */
     /* tw_solve_batch: graphs with n <= 48 run in one persistent launch, each with
        its own state arena (all levels of its current bound) and hash table. */
-    uint64_t batch_graph_states; /* arena states per graph (0 = 2^20); a graph that outgrows its
-                                    arena or table is re-solved alone by the tw_solve path */
+    uint64_t batch_graph_states; /* arena states per graph (0 = as many as half the free device memory
+                                    allows, 2^16..2^22); a graph that outgrows its arena or table is
+                                    re-solved alone by the tw_solve path */
     uint32_t batch_chunk;     /* states per work-queue task, multiple of 64 (0 = 256) */
 } tw_options;
 

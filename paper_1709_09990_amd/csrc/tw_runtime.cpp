@@ -942,11 +942,20 @@ bool read_weights(const char *path, std::vector<float> &params)
     return ok;
 }
 
-// Learned start bounds and arena sizes for graphs ids (network outputs: tw/n
-// and log2(peak + 1)/32).  The start bound is the prediction rounded down
-// (a NO below tw costs less than a YES above it), clamped to [lb, n-2].
+// Learned start bounds and admission for graphs ids (network outputs: tw/n
+// and log2(peak + 1)/32).
+//  - Start bound: one below the prediction rounded down, clamped to [lb, n-2].
+//    Starting at tw-1 costs nothing extra (the NO at tw-1 certifies the answer
+//    anyway), while starting above tw adds a YES run at a larger bound, the
+//    most expensive kind; so errors are pushed downwards.
+//  - Admission: the arena of a batched graph is 16 x the predicted peak level
+//    (never below the default); a graph whose arena would exceed kArenaMax is
+//    sent to the single-graph path at once instead of overflowing in the batch.
+constexpr uint64_t kArenaMax = 1ull << 23;
+
 tw_status predict_starts(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<int> &lbs,
-                         const std::vector<int> &ids, std::vector<int> &k0s, std::vector<uint64_t> &arena_of)
+                         const std::vector<int> &ids, std::vector<int> &k0s, std::vector<uint64_t> &arena_of,
+                         std::vector<char> *too_big = nullptr)
 {
     if (!c->net || ids.empty())
         return TW_OK;
@@ -963,12 +972,15 @@ tw_status predict_starts(tw_ctx *c, const std::vector<Graph> &graphs, const std:
         const int t = ids[q];
         const int n = graphs[(size_t)t].n;
         const double tw_pred = (double)pred[2 * q] * n;
-        int k0 = (int)std::floor(tw_pred);
+        int k0 = (int)std::floor(tw_pred) - 1;
         k0 = std::max(lbs[(size_t)t], std::min(k0, n - 2));
         k0s[(size_t)t] = k0;
         const double peak = std::exp2(std::min(40.0, std::max(0.0, 32.0 * (double)pred[2 * q + 1]))) - 1.0;
-        const uint64_t want = (uint64_t)std::max(4096.0, std::min(16.0 * peak, (double)(1ull << 22)));
-        arena_of[(size_t)t] = pow2_at_least(want);
+        const double want = 16.0 * peak;
+        if (too_big && want > (double)kArenaMax)
+            (*too_big)[(size_t)t] = 1;
+        arena_of[(size_t)t] = std::max<uint64_t>(arena_of[(size_t)t],
+                                                 pow2_at_least((uint64_t)std::min(want, (double)kArenaMax)));
     }
     return TW_OK;
 }
@@ -1192,7 +1204,18 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
     std::vector<GraphOutcome> outcomes(count);
     std::vector<int> batch_ids;   // graphs that go into the persistent launch
     std::vector<int> single_ids;  // graphs solved one at a time
-    const uint64_t default_arena = c->opt.batch_graph_states ? c->opt.batch_graph_states : (1ull << 20);
+    // default arena: as large as half of free device memory allows over the
+    // batch (17 bytes per state: key, creator byte, table slot), 2^16..2^22
+    uint64_t default_arena = c->opt.batch_graph_states;
+    if (!default_arena) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
+            free_b = (size_t)16 << 30;
+        const uint64_t per = (uint64_t)(free_b / 2) / std::max<uint64_t>(1, count) / 17;
+        default_arena = 1ull << 16;
+        while (default_arena < (1ull << 22) && default_arena * 2 <= per)
+            default_arena *= 2;
+    }
     size_t off = 0;
     for (uint32_t t = 0; t < count; ++t) {
         offs[t] = off;
@@ -1220,12 +1243,24 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
     }
     std::vector<int> learned_ids = batch_ids;
     learned_ids.insert(learned_ids.end(), single_ids.begin(), single_ids.end());
-    tw_status st = predict_starts(c, graphs, lbs, learned_ids, k0s, arena_of);
+    std::vector<char> too_big(count, 0);
+    tw_status st = predict_starts(c, graphs, lbs, learned_ids, k0s, arena_of, &too_big);
     if (st != TW_OK)
         return st;
     if (c->opt.batch_graph_states)
         for (int t : batch_ids)
             arena_of[(size_t)t] = c->opt.batch_graph_states;
+    else if (c->net) {
+        // admission: graphs predicted to outgrow any arena skip the batch
+        std::vector<int> keep;
+        for (int t : batch_ids) {
+            if (too_big[(size_t)t])
+                single_ids.push_back(t);
+            else
+                keep.push_back(t);
+        }
+        batch_ids.swap(keep);
+    }
     st = batch_run(c, graphs, lbs, k0s, arena_of, batch_ids, out_tw, out_orders, offs, out_status, single_ids,
                    outcomes, rs);
     if (st != TW_OK)
