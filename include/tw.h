@@ -85,6 +85,11 @@ typedef struct {
     int timing;               /* 1: time every expansion launch with HIP events (tw_stats.kernel_*) */
     int probe;                /* exact table probe: 0 = default, 1 = compare-and-swap only,
                                  2 = plain load first, CAS only on an empty slot */
+    int partition;            /* exact insert: 0 or 1 = single phase (default), 2 = two phases: expand
+                                 and scatter the feasible pairs into hash-range partitions, then insert
+                                 partition by partition into table slices of <= 64 MB (n <= 58).  The
+                                 two-phase form keeps the probes in the Infinity Cache but pays a
+                                 second pass; it measured slower on MI355X for the levels tried */
     /* tw_solve_batch: graphs with n <= 48 run in one persistent launch, each with
        its own state arena (all levels of its current bound) and hash table. */
     uint64_t batch_graph_states; /* arena states per graph (0 = as many as half the free device memory

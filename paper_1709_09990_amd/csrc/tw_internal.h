@@ -37,6 +37,32 @@ struct LevelArgs {
     uint64_t bloom_mask;
 };
 
+// Partitioned insert (large levels): phase 1 writes every feasible (S, v) as
+// one 64-bit entry (state | v << 58) into partition p of the successor buffer;
+// phase 2 inserts partition by partition into that partition's table slice.
+// Each partition is split into kSubRegions regions with their own counters
+// (wave w appends to region w mod kSubRegions), so the flush atomics spread
+// over P * kSubRegions addresses instead of P.
+struct ScatterArgs {
+    uint64_t *parts;        // P * kSubRegions regions of sub_cap entries
+    uint64_t sub_cap;
+    unsigned long long *sub_count;   // [P * kSubRegions] entries claimed (may exceed sub_cap: overflow)
+    int P;
+};
+
+struct GatherArgs {
+    const uint64_t *parts;
+    uint64_t sub_cap;
+    const uint64_t *chunk_prefix;    // [P*kSubRegions+1] exclusive prefix of 64-entry chunks per region
+    const uint64_t *count;           // [P*kSubRegions] entries per region
+    int P;
+    uint64_t slice;                  // table slots per partition
+};
+
+constexpr int kMaxParts = 64;
+constexpr int kSubRegions = 64;
+constexpr int kEntryVShift = 58;     // entries carry v above bit 58 (n <= 58)
+
 constexpr int kBloomProbes = 17;     // hash functions per state (§3.2)
 constexpr int kBloomBitsPerState = 24;  // m / n lower bound (§3.2)
 
@@ -46,6 +72,8 @@ constexpr int kWavesPerBlock = kBlock / 64;
 hipError_t launch_fill_empty(void *table, uint64_t bytes, hipStream_t s);
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_expand(const LevelArgs &a, unsigned grid_blocks, hipStream_t s);
+hipError_t launch_scatter(const LevelArgs &a, const ScatterArgs &sc, unsigned grid_blocks, hipStream_t s);
+hipError_t launch_gather(const LevelArgs &a, const GatherArgs &ga, unsigned grid_blocks, hipStream_t s);
 hipError_t launch_find(const void *keys, uint64_t count, uint64_t target, int key_bytes,
                        unsigned long long *result, hipStream_t s);
 hipError_t launch_zero_counters(LevelCounters *c, hipStream_t s);

@@ -164,20 +164,46 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
             if (kBloom) {
                 if (feas)
                     won = bloom_insert(a.bloom, a.bloom_mask, (uint64_t)key);
+            } else if (feas && a.read_first) {
+                // Linear probing over 16-byte buckets of W = 16 / sizeof(K) slots,
+                // each read with one load.  Within a level a slot only goes from
+                // EMPTY to a key, so a key seen in the copy is final; an EMPTY in
+                // the copy may be stale and is claimed with a CAS, whose returned
+                // value replaces it in the copy.  Slots are taken in bucket order,
+                // so a key is never placed after a slot that was EMPTY.
+                constexpr int W = 16 / (int)sizeof(K);
+                using Vec = unsigned __attribute__((ext_vector_type(4)));
+                const uint64_t nb = a.table_slots / W;
+                uint64_t b = __umul64hi(slot_hash((uint64_t)key), nb);
+                for (uint32_t p = 0;; ++p) {
+                    const Vec raw = *(const Vec *)(table + b * W);
+                    K slot[W];
+                    __builtin_memcpy(slot, &raw, 16);
+                    bool done = false;
+#pragma unroll
+                    for (int j = 0; j < W; ++j) {
+                        if (!done && slot[j] == EMPTY) {
+                            const K old = cas<K>(&table[b * W + j], EMPTY, key);
+                            won = old == EMPTY;
+                            slot[j] = won ? key : old;
+                        }
+                        done |= slot[j] == key;
+                    }
+                    if (done)
+                        break;
+                    if (p >= a.max_probe) {
+                        atomicOr(&a.ctr->overflow, 1u);
+                        break;
+                    }
+                    b = b + 1 == nb ? 0 : b + 1;
+                }
             } else if (feas) {
                 uint64_t h = slot_in((uint64_t)key, a.table_slots);
                 for (uint32_t p = 0;; ++p) {
-                    // Within a level a slot only ever goes from EMPTY to a key,
-                    // so a loaded key is final: only an EMPTY slot needs the CAS.
-                    K old = EMPTY;
-                    if (a.read_first)
-                        old = __hip_atomic_load(&table[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const K old = cas<K>(&table[h], EMPTY, key);
                     if (old == EMPTY) {
-                        old = cas<K>(&table[h], EMPTY, key);
-                        if (old == EMPTY) {
-                            won = true;
-                            break;
-                        }
+                        won = true;
+                        break;
                     }
                     if (old == key)
                         break;
@@ -205,6 +231,210 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
     flush();
     if (lane == 0 && feasible)
         atomicAdd(&a.ctr->successors, (unsigned long long)feasible);
+}
+
+// ---------------------------------------------------------------------------
+// Partitioned insert for large levels.  The random probes of a single-phase
+// insert each pull a whole cache line from HBM when the table is larger than
+// the caches.  Phase 1 (scatter_kernel) expands as above but writes each
+// feasible (S, v) as one entry into partition p (hash range) of a successor
+// buffer, through per-wave LDS buckets flushed 8 entries (64 bytes) at a time.
+// Phase 2 (gather_kernel) walks the partitions in order, so at any moment the
+// waves probe one table slice small enough to stay in the Infinity Cache.
+// ---------------------------------------------------------------------------
+
+constexpr int kBucket = 8;
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void scatter_kernel(LevelArgs a, ScatterArgs sc)
+{
+    __shared__ uint64_t bucket[kWavesPerBlock][kMaxParts][kBucket];
+    __shared__ uint32_t bcount[kWavesPerBlock][kMaxParts];
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = (int)(threadIdx.x >> 6);
+    const K *in = (const K *)a.in;
+    const uint64_t lanebit = 1ull << lane;
+    const uint64_t Aj = lane < a.n ? a.adj[lane] : 0ull;
+    const uint64_t wave_id = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
+    const uint64_t n_waves = (uint64_t)gridDim.x * kWavesPerBlock;
+    bcount[wv][lane] = 0;
+    wave_lds_sync();
+
+    uint64_t feasible = 0;
+    bool overflow = false;  // wave-uniform
+    const uint64_t sub = wave_id % kSubRegions;
+    auto region = [&](int p) { return (uint64_t)p * kSubRegions + sub; };
+    auto flush_bucket = [&](int p, uint32_t cnt) {
+        uint64_t base = 0;
+        if (lane == 0)
+            base = atomicAdd(&sc.sub_count[region(p)], (unsigned long long)cnt);
+        base = read_lane64(base, 0);
+        if (base + cnt > sc.sub_cap)
+            overflow = true;
+        else if ((uint32_t)lane < cnt)
+            sc.parts[region(p) * sc.sub_cap + base + (uint64_t)lane] = bucket[wv][p][lane];
+    };
+
+    for (uint64_t chunk = wave_id * 64; chunk < a.in_count && !overflow; chunk += n_waves * 64) {
+        unsigned int ovf = __hip_atomic_load(&a.ctr->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__builtin_amdgcn_readfirstlane(ovf))
+            break;
+        const uint64_t idx = chunk + (uint64_t)lane;
+        const uint64_t mine = idx < a.in_count ? (uint64_t)in[idx] : 0ull;
+        const uint64_t left = a.in_count - chunk;
+        const int cnt = left < 64 ? (int)left : 64;
+        for (int s = 0; s < cnt; ++s) {
+            const uint64_t S = read_lane64(mine, s);
+            const bool feas = lane_feasible(S, Aj, lane, a.n, a.k) && ((a.allowed >> lane) & 1ull);
+            const uint64_t fmask = ballot(feas);
+            feasible += (uint64_t)__popcll(fmask);
+            if (fmask == 0ull)
+                continue;
+            int p = 0;
+            uint32_t pos = kBucket;
+            bool lane_ovf = false;
+            if (feas) {
+                const uint64_t key = S | lanebit;
+                const uint64_t entry = key | ((uint64_t)lane << kEntryVShift);
+                p = (int)(((slot_hash(key) >> 32) * (uint64_t)sc.P) >> 32);
+                pos = atomicAdd(&bcount[wv][p], 1u);
+                if (pos < (uint32_t)kBucket) {
+                    bucket[wv][p][pos] = entry;
+                } else {
+                    // bucket filled earlier in this step: write straight through
+                    const uint64_t at = atomicAdd(&sc.sub_count[region(p)], 1ull);
+                    if (at < sc.sub_cap)
+                        sc.parts[region(p) * sc.sub_cap + at] = entry;
+                    else
+                        lane_ovf = true;
+                }
+            }
+            if (ballot(lane_ovf))
+                overflow = true;
+            uint64_t full = ballot(feas && pos == (uint32_t)kBucket - 1);
+            if (full) {
+                wave_lds_sync();
+                while (full) {
+                    const int l = __builtin_ctzll(full);
+                    full &= full - 1;
+                    const int pf = __builtin_amdgcn_readlane(p, l);
+                    flush_bucket(pf, kBucket);
+                    if (lane == 0)
+                        bcount[wv][pf] = 0;
+                }
+                wave_lds_sync();
+            }
+        }
+    }
+    wave_lds_sync();
+    for (int p = 0; p < sc.P && !overflow; ++p) {
+        uint32_t c = first_lane32(bcount[wv][p]);
+        c = c > (uint32_t)kBucket ? (uint32_t)kBucket : c;
+        if (c)
+            flush_bucket(p, c);
+    }
+    if (lane == 0) {
+        if (overflow)
+            atomicOr(&a.ctr->overflow, 1u);
+        if (feasible)
+            atomicAdd(&a.ctr->successors, (unsigned long long)feasible);
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void gather_kernel(LevelArgs a, GatherArgs ga)
+{
+    __shared__ K stage_key[kWavesPerBlock][kStage];
+    __shared__ uint8_t stage_v[kWavesPerBlock][kStage];
+    const K EMPTY = (K)~(K)0;
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = (int)(threadIdx.x >> 6);
+    K *out = (K *)a.out;
+    K *table = (K *)a.table;
+    const uint64_t wave_id = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
+    const uint64_t n_waves = (uint64_t)gridDim.x * kWavesPerBlock;
+    const uint64_t total = ga.chunk_prefix[(uint64_t)ga.P * kSubRegions];
+    const uint64_t vmask = (1ull << kEntryVShift) - 1;
+    uint32_t staged = 0;
+
+    auto flush = [&]() {
+        if (staged == 0)
+            return;
+        wave_lds_sync();
+        uint64_t base = 0;
+        if (lane == 0)
+            base = atomicAdd(&a.ctr->out_count, (unsigned long long)staged);
+        base = read_lane64(base, 0);
+        if (base + staged > a.out_cap) {
+            if (lane == 0)
+                atomicOr(&a.ctr->overflow, 1u);
+        } else {
+            for (uint32_t t = (uint32_t)lane; t < staged; t += 64) {
+                out[base + t] = stage_key[wv][t];
+                a.out_lastv[base + t] = stage_v[wv][t];
+            }
+        }
+        wave_lds_sync();
+        staged = 0;
+    };
+
+    for (uint64_t c = wave_id; c < total; c += n_waves) {
+        unsigned int ovf = __hip_atomic_load(&a.ctr->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__builtin_amdgcn_readfirstlane(ovf))
+            break;
+        // region of chunk c: the last r with chunk_prefix[r] <= c (uniform search)
+        int lo = 0, hi = ga.P * kSubRegions;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (ga.chunk_prefix[mid] <= c)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int r = lo;
+        const int p = r / kSubRegions;
+        const uint64_t off = (c - ga.chunk_prefix[r]) * 64 + (uint64_t)lane;
+        const bool valid = off < ga.count[r];
+        const uint64_t entry = valid ? ga.parts[(uint64_t)r * ga.sub_cap + off] : 0ull;
+        const K key = (K)(entry & vmask);
+        const int v = (int)(entry >> kEntryVShift);
+        bool won = false;
+        if (valid) {
+            const uint64_t lo_slot = (uint64_t)p * ga.slice;
+            uint64_t h = lo_slot + (((slot_hash((uint64_t)key) & 0xFFFFFFFFull) * ga.slice) >> 32);
+            const uint64_t hi_slot = lo_slot + ga.slice;
+            for (uint32_t q = 0;; ++q) {
+                K old = __hip_atomic_load(&table[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (old == EMPTY) {
+                    old = cas<K>(&table[h], EMPTY, key);
+                    if (old == EMPTY) {
+                        won = true;
+                        break;
+                    }
+                }
+                if (old == key)
+                    break;
+                if (q >= a.max_probe) {
+                    atomicOr(&a.ctr->overflow, 1u);
+                    break;
+                }
+                h = h + 1 == hi_slot ? lo_slot : h + 1;
+            }
+        }
+        const uint64_t winners = ballot(won);
+        const uint32_t nw = (uint32_t)__popcll(winners);
+        if (nw == 0)
+            continue;
+        if (staged + nw > (uint32_t)kStage)
+            flush();
+        if (won) {
+            const uint32_t pos = staged + (uint32_t)lanes_below(winners);
+            stage_key[wv][pos] = key;
+            stage_v[wv][pos] = (uint8_t)v;
+        }
+        staged += nw;
+    }
+    flush();
 }
 
 __global__ void fill_empty_kernel(uint4 *p, uint64_t n16)
@@ -296,6 +526,26 @@ hipError_t launch_expand(const LevelArgs &a, unsigned grid_blocks, hipStream_t s
         else
             hipLaunchKernelGGL((expand_kernel<uint64_t, false>), dim3(grid_blocks), dim3(kBlock), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const LevelArgs &a, const ScatterArgs &sc, unsigned grid_blocks, hipStream_t s)
+{
+    if (a.in_count == 0)
+        return hipSuccess;
+    if (a.key_bytes == 4)
+        hipLaunchKernelGGL(scatter_kernel<uint32_t>, dim3(grid_blocks), dim3(kBlock), 0, s, a, sc);
+    else
+        hipLaunchKernelGGL(scatter_kernel<uint64_t>, dim3(grid_blocks), dim3(kBlock), 0, s, a, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const LevelArgs &a, const GatherArgs &ga, unsigned grid_blocks, hipStream_t s)
+{
+    if (a.key_bytes == 4)
+        hipLaunchKernelGGL(gather_kernel<uint32_t>, dim3(grid_blocks), dim3(kBlock), 0, s, a, ga);
+    else
+        hipLaunchKernelGGL(gather_kernel<uint64_t>, dim3(grid_blocks), dim3(kBlock), 0, s, a, ga);
     return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tw.h"
+#include "tw.h"
 #include "tw_mpnn.h"
 
 struct tw_mpnn {

@@ -18,7 +18,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tw.h"
+#include "tw.h"
 #include "tw_batch.h"
 #include "tw_internal.h"
 
@@ -55,6 +55,7 @@ struct tw_ctx {
     Buf d_adj, d_ctr, d_find;
     Buf table;               // current hash table (reused between levels)
     Buf bloom;               // Bloom bit array (Bloom variant only)
+    Buf parts, part_meta;    // partitioned insert: successor buffer, counters and prefixes
     LevelCounters *h_ctr = nullptr;      // pinned host mirror
     unsigned long long *h_find = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -376,8 +377,12 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
 
     const float alpha = (c->opt.load_factor > 0.f && c->opt.load_factor <= 0.9f)
                             ? c->opt.load_factor
-                            : 0.5f;
-    double growth = (double)n;  // |level 1| <= n
+                            : 0.25f;
+    size_t dev_free = 0, dev_total = 0;
+    if (hipMemGetInfo(&dev_free, &dev_total) != hipSuccess)
+        dev_free = (size_t)16 << 30;
+    double growth = (double)n;      // |level 1| <= n
+    double pair_ratio = (double)n;  // feasible pairs per state of the previous level
     Buf scratch_keys, scratch_lastv;
     tw_status status = TW_OK;
     uint64_t cur = 1;
@@ -401,7 +406,9 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
             guess = (uint64_t)std::min<double>((double)in_count * std::max(1.0, growth) * 1.3 + 4096.0,
                                                1.8e19);
         guess = std::max<uint64_t>(std::min(guess, bound), 1);
-        float a_eff = alpha;
+        // a sparse table (fewer probes) while it takes at most a third of free memory
+        float a_eff = std::max(alpha, std::min(0.5f, (float)((double)guess * kb * 3.0 / (double)dev_free)));
+        uint64_t part_guess = 0;  // successor-buffer entries (partitioned insert)
 
         uint64_t out_count = 0, succ = 0;
         for (;;) {
@@ -409,6 +416,35 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
                 guess = std::max<uint64_t>(c->opt.max_states, 1);
             // table of any size (multiply-shift slot mapping), a multiple of 64 slots
             uint64_t slots = ((uint64_t)((double)guess / a_eff) + 64 + 63) / 64 * 64;
+            // large tables: partition the insert by hash range into slices of <= 64 MB
+            int P = 1;
+            uint64_t slice = slots, part_cap = 0;
+            if (!bloom && n <= 58 && c->opt.partition != 1) {
+                const uint64_t tbytes = slots * (uint64_t)kb;
+                const uint64_t limit = 64ull << 20;
+                if (c->opt.partition == 2)
+                    P = (int)std::min<uint64_t>(twk::kMaxParts, std::max<uint64_t>(2, (tbytes + limit - 1) / limit));
+            }
+            if (P > 1) {
+                slice = ((slots + (uint64_t)P - 1) / (uint64_t)P + 63) / 64 * 64;
+                slots = slice * (uint64_t)P;
+                if (!part_guess)
+                    part_guess = (uint64_t)std::min<double>((double)in_count * pair_ratio * 1.3 + 4096.0 * P,
+                                                            (double)pairs + 64.0 * P);
+                // entries per sub-region: an equal share of the guess plus slack
+                const uint64_t regions = (uint64_t)P * twk::kSubRegions;
+                part_cap = (uint64_t)(1.1 * (double)part_guess / (double)regions) + 64;
+                tw_status ps = acquire(c, c->parts, part_cap * regions * 8);
+                if (ps == TW_OK)
+                    ps = acquire(c, c->part_meta, (regions * 3 + 1) * 8);
+                if (ps != TW_OK) {
+                    // no room for the successor buffer: single-phase insert for this level
+                    release(c, c->parts);
+                    c->err.clear();
+                    P = 1;
+                    slice = slots;
+                }
+            }
             uint64_t out_cap = std::min<uint64_t>(bound, std::max<uint64_t>(guess, (uint64_t)(0.6 * (double)slots)));
             if (c->opt.max_states)
                 out_cap = std::min<uint64_t>(out_cap, c->opt.max_states);
@@ -463,11 +499,74 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
             const uint64_t waves = (in_count + 63) / 64;
             uint64_t blocks = (waves + twk::kWavesPerBlock - 1) / twk::kWavesPerBlock;
             blocks = std::min<uint64_t>(std::max<uint64_t>(blocks, 1), (uint64_t)c->cu_count * 8);
-            if (c->opt.timing)
-                HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-            HIP_TRY(c, twk::launch_expand(a, (unsigned)blocks, c->stream));
-            if (c->opt.timing)
-                HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+            if (P > 1) {
+                // phase 1: expand and scatter every feasible pair into its hash-range partition
+                const int R = P * twk::kSubRegions;
+                twk::ScatterArgs sc{};
+                sc.parts = (uint64_t *)c->parts.p;
+                sc.sub_cap = part_cap;
+                sc.sub_count = (unsigned long long *)c->part_meta.p;
+                sc.P = P;
+                HIP_TRY(c, twk::launch_fill_zero(c->part_meta.p, (size_t)R * 8, c->stream));
+                if (c->opt.timing)
+                    HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+                HIP_TRY(c, twk::launch_scatter(a, sc, (unsigned)blocks, c->stream));
+                if (c->opt.timing)
+                    HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+                std::vector<uint64_t> cnt((size_t)R);
+                HIP_TRY(c, hipMemcpyAsync(cnt.data(), c->part_meta.p, (size_t)R * 8, hipMemcpyDeviceToHost,
+                                          c->stream));
+                HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr.p, sizeof(LevelCounters), hipMemcpyDeviceToHost,
+                                          c->stream));
+                HIP_TRY(c, hipStreamSynchronize(c->stream));
+                if (c->opt.timing) {
+                    float ms = 0.f;
+                    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+                    rs.kernel_seconds += ms * 1e-3;
+                }
+                uint64_t most = 0;
+                for (uint64_t x : cnt)
+                    most = std::max(most, x);
+                if (c->h_ctr->overflow || most > part_cap) {
+                    // successor buffer too small: grow it and replay the level
+                    rs.retries++;
+                    part_guess = std::max<uint64_t>(part_guess * 2, (uint64_t)(1.25 * (double)most * R));
+                    continue;
+                }
+                // phase 2: insert partition by partition (chunk prefix over 64-entry chunks)
+                std::vector<uint64_t> meta((size_t)R * 2 + 1);
+                uint64_t chunks = 0;
+                for (int r = 0; r < R; ++r) {
+                    meta[(size_t)r] = chunks;
+                    chunks += (cnt[(size_t)r] + 63) / 64;
+                }
+                meta[(size_t)R] = chunks;
+                for (int r = 0; r < R; ++r)
+                    meta[(size_t)R + 1 + (size_t)r] = cnt[(size_t)r];
+                uint64_t *dmeta = (uint64_t *)c->part_meta.p + R;
+                HIP_TRY(c, hipMemcpyAsync(dmeta, meta.data(), meta.size() * 8, hipMemcpyHostToDevice, c->stream));
+                twk::GatherArgs ga{};
+                ga.parts = (const uint64_t *)c->parts.p;
+                ga.sub_cap = part_cap;
+                ga.chunk_prefix = dmeta;
+                ga.count = dmeta + R + 1;
+                ga.P = P;
+                ga.slice = slice;
+                const uint64_t gblocks = std::min<uint64_t>(
+                    std::max<uint64_t>((chunks + twk::kWavesPerBlock - 1) / twk::kWavesPerBlock, 1),
+                    (uint64_t)c->cu_count * 8);
+                if (c->opt.timing)
+                    HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+                HIP_TRY(c, twk::launch_gather(a, ga, (unsigned)gblocks, c->stream));
+                if (c->opt.timing)
+                    HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+            } else {
+                if (c->opt.timing)
+                    HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+                HIP_TRY(c, twk::launch_expand(a, (unsigned)blocks, c->stream));
+                if (c->opt.timing)
+                    HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+            }
             HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr.p, sizeof(LevelCounters),
                                       hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -505,6 +604,7 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
         rs.peak = std::max(rs.peak, std::max(out_count, in_count));
         run_peak = std::max(run_peak, out_count);
         growth = in_count ? (double)out_count / (double)in_count : 1.0;
+        pair_ratio = in_count ? (double)succ / (double)in_count : (double)n;
 
         // the new level: an exact-size copy when levels are kept, else the scratch pair itself
         Level nl;
@@ -1088,6 +1188,8 @@ void tw_ctx_destroy(tw_ctx *c)
     release(c, c->d_find);
     release(c, c->table);
     release(c, c->bloom);
+    release(c, c->parts);
+    release(c, c->part_meta);
     drop_cache(c);
     if (c->h_ctr)
         (void)hipHostFree(c->h_ctr);

@@ -39,14 +39,11 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Slot hash of a state: two multiply-xorshift rounds.
+// Hash of a state: one xorshift, one multiply by an odd constant (the high
+// bits are used: a range reduction takes the top of hash * size).
 __device__ __forceinline__ uint64_t slot_hash(uint64_t key)
 {
-    uint64_t h = key * 0xD6E8FEB86659FD93ull;
-    h ^= h >> 32;
-    h *= 0xD6E8FEB86659FD93ull;
-    h ^= h >> 32;
-    return h;
+    return (key ^ (key >> 29)) * 0x9E3779B97F4A7C15ull;
 }
 
 // |Q(S, v)| <= k for this lane's vertex v (§2).  Components of G[S] by ballot

@@ -43,6 +43,7 @@ class _Options(ctypes.Structure):
         ("capacity_override", ctypes.c_uint64),
         ("timing", ctypes.c_int),
         ("probe", ctypes.c_int),
+        ("partition", ctypes.c_int),
         ("batch_graph_states", ctypes.c_uint64),
         ("batch_chunk", ctypes.c_uint32),
     ]
@@ -197,7 +198,7 @@ class Context:
     def __init__(self, device: int = 0, stream=None, dedup: int = TW_DEDUP_EXACT,
                  load_factor: float = 0.0, max_states: int = 0, capacity_override: int = 0,
                  timing: bool = False, k_policy: int = TW_K_ASCENDING, weights_path: str | None = None,
-                 batch_graph_states: int = 0, batch_chunk: int = 0, probe: int = 0):
+                 batch_graph_states: int = 0, batch_chunk: int = 0, probe: int = 0, partition: int = 0):
         L = load()
         self._L = L
         o = _Options()
@@ -213,6 +214,7 @@ class Context:
         o.capacity_override = capacity_override
         o.timing = 1 if timing else 0
         o.probe = probe
+        o.partition = partition
         o.batch_graph_states = batch_graph_states
         o.batch_chunk = batch_chunk
         h = ctypes.c_void_p()

@@ -366,3 +366,29 @@ def test_autotune_candidates_agree(tmp_path, monkeypatch):
     opts = autotune.tuned_options(graphs, sample=24)
     assert set(opts) == {"batch_chunk", "load_factor", "probe"}
     assert autotune.tuned_options(graphs) == opts
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: G.workload_single_small(1001),
+    lambda: G.gnp(26, 0.2, 13001),
+    lambda: G.gnp(38, 0.35, 12002),
+    lambda: G.grid(3, 12),
+    lambda: G.gnp(56, 0.45, 12010),
+])
+def test_partitioned_insert_levels_match(oracle, maker):
+    """The two-phase insert (expand + scatter by hash range, then insert
+    partition by partition), forced at small sizes: every level equals the
+    oracle's, with the same feasible-pair counts; also under overflow replay."""
+    from paper_1709_09990_amd import tw as T
+    rows = maker()
+    tw = oracle.treewidth_bfs(rows, oracle.mmw(rows))
+    for kw in ({"partition": 2}, {"partition": 2, "capacity_override": 7}):
+        with T.Context(device=0, **kw) as c:
+            got, order, _ = c.solve(rows)
+            assert got == tw and oracle.order_width(rows, order) == tw
+            for k in (tw - 1, tw):
+                if k < 0:
+                    continue
+                _, ref_levels, ref_stats = oracle.decide(rows, k)
+                _, levels = c.trace_decide(rows, k)
+                _check_levels(oracle, rows, k, levels, ref_levels, ref_stats)
