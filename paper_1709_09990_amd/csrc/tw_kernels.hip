@@ -18,7 +18,7 @@
 namespace twk {
 namespace {
 
-constexpr int kStage = 512;  // winners a wave stages in LDS before appending
+constexpr int kStage = 384;  // winners a wave stages in LDS before appending (8 blocks fit a CU)
 
 __device__ __forceinline__ uint64_t rotl64(uint64_t x, int r)
 {
@@ -98,25 +98,93 @@ __device__ __forceinline__ uint64_t cas<uint64_t>(uint64_t *p, uint64_t e, uint6
                                (unsigned long long)d);
 }
 
+// Inserts `key` into the exact table; true iff this call stored it.
+// read_first: linear probing over 16-byte buckets of W = 16 / sizeof(K) slots,
+// each read with one load.  Within a level a slot only goes from EMPTY to a
+// key, so a key seen in the copy is final; an EMPTY in the copy may be stale
+// and is claimed with a CAS, whose returned value replaces it in the copy.
+// Slots are taken in bucket order, so a key is never placed after a slot that
+// was EMPTY.  Otherwise: one CAS per slot, slot by slot.
+template <typename K>
+__device__ __forceinline__ bool table_insert(const LevelArgs &a, K *table, K key)
+{
+    const K EMPTY = (K)~(K)0;
+    bool won = false;
+    if (a.read_first) {
+        constexpr int W = 16 / (int)sizeof(K);
+        using Vec = unsigned __attribute__((ext_vector_type(4)));
+        const uint64_t nb = a.table_slots / W;
+        uint64_t b = __umul64hi(slot_hash((uint64_t)key), nb);
+        for (uint32_t p = 0;; ++p) {
+            const Vec raw = *(const Vec *)(table + b * W);
+            K slot[W];
+            __builtin_memcpy(slot, &raw, 16);
+            bool done = false;
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                if (!done && slot[j] == EMPTY) {
+                    const K old = cas<K>(&table[b * W + j], EMPTY, key);
+                    won = old == EMPTY;
+                    slot[j] = won ? key : old;
+                }
+                done |= slot[j] == key;
+            }
+            if (done)
+                break;
+            if (p >= a.max_probe) {
+                atomicOr(&a.ctr->overflow, 1u);
+                break;
+            }
+            b = b + 1 == nb ? 0 : b + 1;
+        }
+    } else {
+        uint64_t h = slot_in((uint64_t)key, a.table_slots);
+        for (uint32_t p = 0;; ++p) {
+            const K old = cas<K>(&table[h], EMPTY, key);
+            if (old == EMPTY) {
+                won = true;
+                break;
+            }
+            if (old == key)
+                break;
+            if (p >= a.max_probe) {
+                atomicOr(&a.ctr->overflow, 1u);
+                break;
+            }
+            h = h + 1 == a.table_slots ? 0 : h + 1;
+        }
+    }
+    return won;
+}
+
+// Expansion of one level.  Each wave walks chunks of 64 input states; per
+// state it finds the feasible lanes and appends their successors to a
+// per-wave LDS queue.  Whenever 64 are queued the wave inserts them with all
+// 64 lanes at once, so the probes of a wave run at full width and one memory
+// round trip serves 64 successors rather than the few of one state.
 template <typename K, bool kBloom>
 __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
 {
+    constexpr uint32_t kQueue = 128;  // ring of pending successors per wave
     __shared__ K stage_key[kWavesPerBlock][kStage];
     __shared__ uint8_t stage_v[kWavesPerBlock][kStage];
+    __shared__ K queue_key[kWavesPerBlock][kQueue];
+    __shared__ uint8_t queue_v[kWavesPerBlock][kQueue];
 
-    const K EMPTY = (K)~(K)0;
     const int lane = (int)(threadIdx.x & 63);
     const int wv = (int)(threadIdx.x >> 6);
     const K *in = (const K *)a.in;
     K *out = (K *)a.out;
     K *table = (K *)a.table;
-    const uint64_t lanebit = 1ull << lane;
     const uint64_t Aj = lane < a.n ? a.adj[lane] : 0ull;
+    const bool lane_allowed = ((a.allowed >> lane) & 1ull) != 0ull;
 
     const uint64_t wave_id = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
     const uint64_t n_waves = (uint64_t)gridDim.x * kWavesPerBlock;
 
     uint32_t staged = 0;       // wave-uniform
+    uint32_t qhead = 0;        // wave-uniform ring position of the oldest queued successor
+    uint32_t qcount = 0;       // wave-uniform
     uint64_t feasible = 0;     // wave-uniform count of feasible pairs
 
     // Append the staged winners to the next level (one atomic per batch).
@@ -141,6 +209,41 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
         staged = 0;
     };
 
+    // Insert the m (<= 64) oldest queued successors, one per lane.
+    auto drain = [&](uint32_t m) {
+        wave_lds_sync();
+        const bool have = (uint32_t)lane < m;
+        K key = 0;
+        uint8_t v = 0;
+        if (have) {
+            const uint32_t at = (qhead + (uint32_t)lane) & (kQueue - 1);
+            key = queue_key[wv][at];
+            v = queue_v[wv][at];
+        }
+        wave_lds_sync();
+        qhead = (qhead + m) & (kQueue - 1);
+        qcount -= m;
+        bool won = false;
+        if (have) {
+            if (kBloom)
+                won = bloom_insert(a.bloom, a.bloom_mask, (uint64_t)key);
+            else
+                won = table_insert<K>(a, table, key);
+        }
+        const uint64_t winners = ballot(won);
+        const uint32_t nw = (uint32_t)__popcll(winners);
+        if (nw == 0)
+            return;
+        if (staged + nw > (uint32_t)kStage)
+            flush();
+        if (won) {
+            const uint32_t pos = staged + (uint32_t)lanes_below(winners);
+            stage_key[wv][pos] = key;
+            stage_v[wv][pos] = v;
+        }
+        staged += nw;
+    };
+
     for (uint64_t chunk = wave_id * 64; chunk < a.in_count; chunk += n_waves * 64) {
         unsigned int ovf = __hip_atomic_load(&a.ctr->overflow, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
@@ -153,81 +256,25 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
 
         for (int s = 0; s < cnt; ++s) {
             const uint64_t S = read_lane64(mine, s);
-            const bool feas = lane_feasible(S, Aj, lane, a.n, a.k) && ((a.allowed >> lane) & 1ull);
+            const bool feas = lane_feasible(S, Aj, lane, a.n, a.k) && lane_allowed;
             const uint64_t feas_mask = ballot(feas);
-            feasible += (uint64_t)__popcll(feas_mask);
-            if (feas_mask == 0ull)
+            const uint32_t nf = (uint32_t)__popcll(feas_mask);
+            feasible += nf;
+            if (nf == 0)
                 continue;
-
-            bool won = false;
-            const K key = (K)(S | lanebit);
-            if (kBloom) {
-                if (feas)
-                    won = bloom_insert(a.bloom, a.bloom_mask, (uint64_t)key);
-            } else if (feas && a.read_first) {
-                // Linear probing over 16-byte buckets of W = 16 / sizeof(K) slots,
-                // each read with one load.  Within a level a slot only goes from
-                // EMPTY to a key, so a key seen in the copy is final; an EMPTY in
-                // the copy may be stale and is claimed with a CAS, whose returned
-                // value replaces it in the copy.  Slots are taken in bucket order,
-                // so a key is never placed after a slot that was EMPTY.
-                constexpr int W = 16 / (int)sizeof(K);
-                using Vec = unsigned __attribute__((ext_vector_type(4)));
-                const uint64_t nb = a.table_slots / W;
-                uint64_t b = __umul64hi(slot_hash((uint64_t)key), nb);
-                for (uint32_t p = 0;; ++p) {
-                    const Vec raw = *(const Vec *)(table + b * W);
-                    K slot[W];
-                    __builtin_memcpy(slot, &raw, 16);
-                    bool done = false;
-#pragma unroll
-                    for (int j = 0; j < W; ++j) {
-                        if (!done && slot[j] == EMPTY) {
-                            const K old = cas<K>(&table[b * W + j], EMPTY, key);
-                            won = old == EMPTY;
-                            slot[j] = won ? key : old;
-                        }
-                        done |= slot[j] == key;
-                    }
-                    if (done)
-                        break;
-                    if (p >= a.max_probe) {
-                        atomicOr(&a.ctr->overflow, 1u);
-                        break;
-                    }
-                    b = b + 1 == nb ? 0 : b + 1;
-                }
-            } else if (feas) {
-                uint64_t h = slot_in((uint64_t)key, a.table_slots);
-                for (uint32_t p = 0;; ++p) {
-                    const K old = cas<K>(&table[h], EMPTY, key);
-                    if (old == EMPTY) {
-                        won = true;
-                        break;
-                    }
-                    if (old == key)
-                        break;
-                    if (p >= a.max_probe) {
-                        atomicOr(&a.ctr->overflow, 1u);
-                        break;
-                    }
-                    h = h + 1 == a.table_slots ? 0 : h + 1;
-                }
+            // qcount < 64 here and nf <= 64, so the ring of 128 never overruns
+            if (feas) {
+                const uint32_t at = (qhead + qcount + (uint32_t)lanes_below(feas_mask)) & (kQueue - 1);
+                queue_key[wv][at] = (K)(S | (1ull << lane));
+                queue_v[wv][at] = (uint8_t)lane;
             }
-            const uint64_t winners = ballot(won);
-            const uint32_t nw = (uint32_t)__popcll(winners);
-            if (nw == 0)
-                continue;
-            if (staged + nw > (uint32_t)kStage)
-                flush();
-            if (won) {
-                const uint32_t pos = staged + (uint32_t)lanes_below(winners);
-                stage_key[wv][pos] = key;
-                stage_v[wv][pos] = (uint8_t)lane;
-            }
-            staged += nw;
+            qcount += nf;
+            if (qcount >= 64)
+                drain(64);
         }
     }
+    while (qcount)
+        drain(qcount < 64 ? qcount : 64);
     flush();
     if (lane == 0 && feasible)
         atomicAdd(&a.ctr->successors, (unsigned long long)feasible);
