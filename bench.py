@@ -17,7 +17,11 @@ Prints one JSON line.  Fields beyond the driver's contract:
   roofline      the expansion kernel against HBM bandwidth, algorithmic bytes
                 (key read per state, one compare-and-swap per feasible pair,
                 key + creator byte written per new state) over the kernel time
-                measured with HIP events on the launching stream
+                measured with HIP events on the launching stream; `traffic` is
+                the counter-measured bytes per launch of the committed
+                rocprofv3 summary (null once the kernel sources change), and
+                `probe_reference` the machine's random-access rate for the
+                insert's access pattern, measured in the same run
   cpu_baseline  the oracle (Listing 1 with exact dedup, plain C + OpenMP) on a
                 bounded prefix of the same workload, on this host's cores
 """
@@ -95,6 +99,23 @@ def copy_probe(nbytes: int, reps: int = 5):
 WEIGHTS = os.path.join(ROOT, "paper_1709_09990_amd", "weights", "mpnn_mixture_n16_30.bin")
 
 
+def probe_reference(kernel_successors_per_s: float) -> dict:
+    """The machine's rate for the insert's access pattern, measured now with
+    tw_probe_rate on an 8 GiB buffer (far above the 256 MB Infinity Cache, as
+    the large levels' tables are): random 16-byte loads with one in flight per
+    lane (the probe), random 64-bit compare-and-swaps, and loads with eight in
+    flight per lane.  The expansion kernel does one probe per feasible pair."""
+    from paper_1709_09990_amd import tw as T
+    nbytes, count = 8 << 30, 1 << 31
+    r = {"buffer_bytes": nbytes, "operations": count}
+    for mode, name in ((0, "random_16B_loads_per_s"), (1, "random_cas64_per_s"),
+                       (2, "random_16B_loads_8_in_flight_per_s")):
+        r[name] = T.probe_rate(nbytes, count, mode)
+    r["kernel_probes_per_s"] = kernel_successors_per_s
+    r["kernel_frac_of_random_loads"] = round(kernel_successors_per_s / r["random_16B_loads_per_s"], 4)
+    return r
+
+
 def batch_leg(count: int = 512):
     """Graphs solved per second, batched: plain ascending-k search vs the
     learned start bound and admission, on held-out graphs of the uneven
@@ -167,6 +188,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched learned-vs-plain leg")
+    ap.add_argument("--no-probe", action="store_true", help="skip the random-access reference measurement")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -215,18 +237,26 @@ def main():
     alg_bytes = w * total["states_expanded"] + w * total["successors"] + (w + 1) * total["unique"]
     ks = total["kernel_seconds"]
     achieved = alg_bytes / ks / 1e9 if ks > 0 else 0.0
+    traffic = measured_traffic()
+    avg_launch_s = ks / max(1, total["launches"])
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 2),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 5),
-        "traffic": measured_traffic(),
+        "traffic": traffic,
         "kernel": "expand_kernel<uint%d>" % (8 * w),
         "launches": total["launches"],
-        "avg_launch_us": round(ks / max(1, total["launches"]) * 1e6, 2),
+        "avg_launch_us": round(avg_launch_s * 1e6, 2),
         "alg_bytes_per_launch": int(alg_bytes / max(1, total["launches"])),
     }
+    if traffic and avg_launch_s > 0:
+        # counter-measured bytes (committed profile) over this run's average launch
+        roofline["traffic_GBps"] = round(traffic / avg_launch_s / 1e9, 1)
+        roofline["traffic_frac"] = round(traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)
+    if not args.no_probe and ks > 0:
+        roofline["probe_reference"] = probe_reference(total["successors"] / ks)
     out = {
         "metric": "(S,v) expansions/sec + graphs solved/sec (learned-k batched vs plain), exact",
         "value": total["expansions"] / elapsed,

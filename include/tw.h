@@ -228,6 +228,17 @@ tw_status tw_mpnn_gradients(tw_mpnn *m, const tw_graph *gs, uint32_t count, cons
 tw_status tw_mpnn_train_step(tw_mpnn *m, const tw_graph *gs, uint32_t count, const float *targets, float lr,
                              float weight_decay, float *out_loss);
 
+/* Machine reference for the table insert (a diagnostic, not part of the
+ * search): times random operations on a fresh device buffer of `bytes` bytes
+ * (>= 4096, allocated and freed by the call) on `device`, with eight
+ * 256-thread workgroups per compute unit like the expansion kernel.  mode 0:
+ * one 16-byte load per operation, one in flight per lane (the probe of the
+ * exact table); 1: one 64-bit compare-and-swap; 2: 16-byte loads, eight in
+ * flight per lane.  *out_seconds is the kernel time (HIP events) scaled to
+ * exactly `count` operations.  TW_EINVAL on a bad argument, TW_ENOMEM if the
+ * buffer does not fit, TW_EDEVICE on a HIP error. */
+tw_status tw_probe_rate(int device, uint64_t bytes, uint64_t count, int mode, double *out_seconds);
+
 const char *tw_status_str(tw_status s);
 /* Message of the last failure on ctx (empty string if none); valid until the next call. */
 const char *tw_last_error(const tw_ctx *ctx);

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "tw.h"
+#include "tw_probe.h"
 #include "tw_batch.h"
 #include "tw_internal.h"
 
@@ -1392,6 +1393,57 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
         }
     add_stats(stats, rs, now_s() - t0);
     return TW_OK;
+}
+
+tw_status tw_probe_rate(int device, uint64_t bytes, uint64_t count, int mode, double *out_seconds)
+{
+    if (!out_seconds || mode < 0 || mode > 2 || bytes < 4096 || count == 0)
+        return TW_EINVAL;
+    *out_seconds = 0.0;
+    if (hipSetDevice(device) != hipSuccess)
+        return TW_EDEVICE;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+        return TW_EDEVICE;
+    const unsigned blocks = (unsigned)cus * 8u;
+    const uint64_t threads = (uint64_t)blocks * twk::kProbeBlock;
+    uint64_t per_thread = (count + threads - 1) / threads;
+    if (mode == 2)
+        per_thread = (per_thread + 7) / 8 * 8;
+    void *buf = nullptr;
+    uint32_t *sink = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    tw_status st = TW_OK;
+    float ms = 0.f;
+    if (hipMalloc(&buf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return TW_ENOMEM;
+    }
+    if (hipMalloc((void **)&sink, 4) != hipSuccess || hipMemset(buf, 0xFF, bytes) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        st = TW_EDEVICE;
+        goto out;
+    }
+    // one untimed pass so the timed one meets warm TLBs
+    if (twk::launch_probe_rate(buf, bytes, per_thread, mode, blocks, sink, nullptr) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess || hipMemset(buf, 0xFF, bytes) != hipSuccess ||
+        hipEventRecord(e0, nullptr) != hipSuccess ||
+        twk::launch_probe_rate(buf, bytes, per_thread, mode, blocks, sink, nullptr) != hipSuccess ||
+        hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = TW_EDEVICE;
+        goto out;
+    }
+    *out_seconds = (double)ms * 1e-3 * (double)count / (double)(per_thread * threads);
+out:
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    if (sink)
+        (void)hipFree(sink);
+    (void)hipFree(buf);
+    return st;
 }
 
 tw_status tw_mmw(const tw_graph *gr, int32_t *out_lb)

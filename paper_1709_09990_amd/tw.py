@@ -97,7 +97,7 @@ EXPORTS = (
     "tw_trace_decide", "tw_mmw", "tw_order_width", "tw_status_str", "tw_last_error",
     "tw_mpnn_param_count", "tw_mpnn_features", "tw_mpnn_create", "tw_mpnn_destroy",
     "tw_mpnn_set_params", "tw_mpnn_get_params", "tw_mpnn_predict", "tw_mpnn_gradients",
-    "tw_mpnn_train_step",
+    "tw_mpnn_train_step", "tw_probe_rate",
 )
 
 _lib = None
@@ -124,6 +124,8 @@ def load():
                                   P(ctypes.c_int32)]
     L.tw_mmw.argtypes = [P(_Graph), P(ctypes.c_int32)]
     L.tw_order_width.argtypes = [P(_Graph), P(ctypes.c_int32), P(ctypes.c_int32)]
+    L.tw_probe_rate.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                P(ctypes.c_double)]
     L.tw_status_str.argtypes = [ctypes.c_int]
     L.tw_status_str.restype = ctypes.c_char_p
     L.tw_last_error.argtypes = [ctypes.c_void_p]
@@ -143,7 +145,8 @@ def load():
                                      ctypes.c_float, f32p]
     for name in ("tw_ctx_create", "tw_decide", "tw_solve", "tw_solve_batch", "tw_trace_decide",
                  "tw_mmw", "tw_order_width", "tw_mpnn_features", "tw_mpnn_create", "tw_mpnn_set_params",
-                 "tw_mpnn_get_params", "tw_mpnn_predict", "tw_mpnn_gradients", "tw_mpnn_train_step"):
+                 "tw_mpnn_get_params", "tw_mpnn_predict", "tw_mpnn_gradients", "tw_mpnn_train_step",
+                 "tw_probe_rate"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -179,6 +182,18 @@ def order_width(rows, order) -> int:
     if st != TW_OK:
         raise TwError(st, L.tw_status_str(st).decode())
     return out.value
+
+
+def probe_rate(bytes_: int, count: int, mode: int = 0, device: int = 0) -> float:
+    """Random operations per second on a device buffer of bytes_ bytes (see
+    tw_probe_rate: mode 0 random 16-byte loads, 1 random 64-bit CAS, 2 loads
+    with eight in flight per lane)."""
+    L = load()
+    sec = ctypes.c_double(0.0)
+    st = L.tw_probe_rate(int(device), int(bytes_), int(count), int(mode), ctypes.byref(sec))
+    if st != TW_OK:
+        raise TwError(st, L.tw_status_str(st).decode())
+    return count / sec.value
 
 
 @dataclass
