@@ -73,6 +73,9 @@ def lib():
         L.tworacle_brute_force.restype = ctypes.c_int
         L.tworacle_bfs_level.argtypes = [ctypes.c_int, u64p, ctypes.c_int, u64p, ctypes.c_int64,
                                          ctypes.POINTER(u64p), i64p, i64p, ctypes.c_int]
+        L.tworacle_bfs_level_masked.argtypes = [ctypes.c_int, u64p, ctypes.c_int, ctypes.c_uint64, u64p,
+                                                ctypes.c_int64, ctypes.POINTER(u64p), i64p, i64p, ctypes.c_int]
+        L.tworacle_bfs_level_masked.restype = ctypes.c_int64
         L.tworacle_free.argtypes = [ctypes.c_void_p]
         L.tworacle_free.restype = None
         L.tworacle_bfs_level.restype = ctypes.c_int64
@@ -202,8 +205,9 @@ def frontiers_from_dp(rows, k: int, table: np.ndarray | None = None) -> list[np.
 # O4: the level search of Listing 1 with exact duplicate removal
 # ---------------------------------------------------------------------------
 
-def bfs_level(rows, k: int, frontier: np.ndarray, threads: int = 0):
-    """One level: returns (next frontier sorted, feasible pairs, candidate pairs)."""
+def bfs_level(rows, k: int, frontier: np.ndarray, threads: int = 0, allowed: int | None = None):
+    """One level: returns (next frontier sorted, feasible pairs, candidate pairs).
+    With `allowed`, only those vertices may be added (candidates count only them)."""
     a = _rows(rows)
     n = len(a)
     f = np.ascontiguousarray(np.asarray(frontier, dtype=np.uint64))
@@ -211,8 +215,13 @@ def bfs_level(rows, k: int, frontier: np.ndarray, threads: int = 0):
     gen = ctypes.c_int64(0)
     cand = ctypes.c_int64(0)
     L = lib()
-    cnt = L.tworacle_bfs_level(n, _p(a, u64p), int(k), _p(f, u64p), len(f), ctypes.byref(ptr),
-                               ctypes.byref(gen), ctypes.byref(cand), threads)
+    if allowed is None:
+        cnt = L.tworacle_bfs_level(n, _p(a, u64p), int(k), _p(f, u64p), len(f), ctypes.byref(ptr),
+                                   ctypes.byref(gen), ctypes.byref(cand), threads)
+    else:
+        cnt = L.tworacle_bfs_level_masked(n, _p(a, u64p), int(k), int(allowed) & (2**64 - 1), _p(f, u64p),
+                                          len(f), ctypes.byref(ptr), ctypes.byref(gen), ctypes.byref(cand),
+                                          threads)
     if cnt < 0:
         raise RuntimeError("oracle bfs_level failed (out of memory?)")
     try:

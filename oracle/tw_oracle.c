@@ -289,9 +289,13 @@ static void radix_sort(uint64_t *a, uint64_t *tmp, int64_t cnt)
  * number, or -1 on a bad argument or allocation failure.  *generated
  * (nullable) receives the number of feasible (S,v) pairs, *candidates
  * (nullable) the number of (S,v) pairs tried. */
-int64_t tworacle_bfs_level(int n, const uint64_t *rows, int k, const uint64_t *in,
-                           int64_t in_count, uint64_t **out,
-                           int64_t *generated, int64_t *candidates, int nthreads)
+/* One level of Listing 1 where only vertices in `allowed` may be added to a
+ * state (all vertices: the plain search; the complement of a maximum clique:
+ * the first optimisation of §3.1, which never picks a clique vertex because
+ * some optimal order eliminates the clique last). */
+int64_t tworacle_bfs_level_masked(int n, const uint64_t *rows, int k, uint64_t allowed,
+                                  const uint64_t *in, int64_t in_count, uint64_t **out,
+                                  int64_t *generated, int64_t *candidates, int nthreads)
 {
     adjlist g;
     if (n < 1 || n > MAXN || in_count < 0)
@@ -321,7 +325,7 @@ int64_t tworacle_bfs_level(int n, const uint64_t *rows, int k, const uint64_t *i
         for (int64_t s = 0; s < in_count; s++) {
             uint64_t S = in[s];
             for (int v = 0; v < n; v++) {
-                if ((S >> v) & 1ULL)
+                if (((S >> v) & 1ULL) || !((allowed >> v) & 1ULL))
                     continue;
                 tried[tid]++;
                 if (q_degree(&g, S, v) <= k) {
@@ -382,6 +386,14 @@ int64_t tworacle_bfs_level(int n, const uint64_t *rows, int k, const uint64_t *i
     free(capb);
     free(tried);
     return result;
+}
+
+int64_t tworacle_bfs_level(int n, const uint64_t *rows, int k, const uint64_t *in,
+                           int64_t in_count, uint64_t **out,
+                           int64_t *generated, int64_t *candidates, int nthreads)
+{
+    return tworacle_bfs_level_masked(n, rows, k, ~0ULL, in, in_count, out, generated, candidates,
+                                     nthreads);
 }
 
 void tworacle_free(void *p)
