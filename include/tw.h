@@ -74,7 +74,8 @@ typedef struct {
     int device;               /* HIP device ordinal */
     void *stream;             /* hipStream_t to launch on, or NULL for a stream the context creates */
     int dedup;                /* TW_DEDUP_EXACT or TW_DEDUP_BLOOM */
-    float load_factor;        /* target hash-table load in (0, 0.9]; 0 picks the default 0.5 */
+    float load_factor;        /* target hash-table load in (0, 0.9]; 0 picks the default 0.25 (raised
+                                 towards 0.5 when the table would take over a third of free memory) */
     int k_policy;             /* TW_K_ASCENDING or TW_K_LEARNED */
     const char *weights_path; /* TW_K_LEARNED: file of network parameters: 8 bytes "TWMPNN01", a
                                  uint32 count (= tw_mpnn_param_count()), then count float32 values,
@@ -96,7 +97,18 @@ typedef struct {
                                     allows, 2^16..2^22); a graph that outgrows its arena or table is
                                     re-solved alone by the tw_solve path */
     uint32_t batch_chunk;     /* states per work-queue task, multiple of 64 (0 = 256) */
+    int reductions;           /* TW_REDUCE_NONE (default): the levels are those of Listing 1.
+                                 TW_REDUCE_CLIQUE_PATHS: the first two optimisations of §3.1 — the
+                                 vertices of a maximum clique C are never added to a state (some optimal
+                                 order ends with C; C is the maximum clique whose ascending vertex list is
+                                 lexicographically smallest), decide(k) is NO without a search when
+                                 k < |C| - 1, and the search for bound k runs on G plus an edge uv for
+                                 every non-adjacent pair joined by >= k + 1 internally vertex-disjoint
+                                 paths in G (counts taken once per graph).  Answers are unchanged; levels
+                                 become {S outside C : |S| = i, S has width <= k in that graph}. */
 } tw_options;
+
+enum { TW_REDUCE_NONE = 0, TW_REDUCE_CLIQUE_PATHS = 1 };
 
 /* Counters of one call (summed over every bound k and level it ran). */
 typedef struct {
@@ -183,6 +195,13 @@ tw_status tw_trace_decide(tw_ctx *ctx, const tw_graph *g, int32_t k,
  * it if isolated, otherwise contracts it into its lowest-index minimum-degree
  * neighbour; the bound is the largest second-smallest degree met. Host only. */
 tw_status tw_mmw(const tw_graph *g, int32_t *out_lb);
+
+/* Host only: what TW_REDUCE_CLIQUE_PATHS uses for g (§3.1).  *out_clique =
+ * the maximum clique it never adds to a state (vertex mask; the one whose
+ * ascending vertex list is lexicographically smallest); out_paths (n*n bytes,
+ * may be NULL) row-major: internally vertex-disjoint u-v path counts for
+ * non-adjacent u != v, capped at 255, 0 on the diagonal and for edges. */
+tw_status tw_reductions(const tw_graph *g, uint64_t *out_clique, uint8_t *out_paths);
 
 /* Width of an elimination order by fill-in (§2); -1 in *out_width if order is
  * not a permutation of 0..n-1.  Host only. */

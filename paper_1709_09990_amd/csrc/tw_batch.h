@@ -45,6 +45,8 @@ struct BatchGraph {
     uint32_t tag;
     uint32_t decisions, levels_run;
     int32_t order[64];       // elimination order of the best YES run (width best_yes)
+    uint64_t allowed;        // vertices that may be added to a state (all, or all but a maximum clique)
+    const uint8_t *paths;    // 64 x 64 disjoint-path counts: bound k adds uv when > k (null: none)
 };
 
 // One level of one graph: nchunks tasks of up to chunk states.

@@ -252,7 +252,16 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
         uint64_t *keys = G->keys;
         uint8_t *lastv = G->lastv;
         uint64_t *table = G->table;
-        const uint64_t Aj = lane < n ? G->adj[lane] : 0ull;
+        uint64_t Aj = lane < n ? G->adj[lane] : 0ull;
+        const uint8_t *paths = G->paths;
+        if (paths && lane < n) {
+            // edges of G_k+: pairs joined by more than k disjoint paths (§3.1)
+            const uint8_t *row = paths + lane * 64;
+            for (int u = 0; u < n; ++u)
+                if ((int)row[u] > k)
+                    Aj |= 1ull << u;
+        }
+        const bool lane_allowed = ((G->allowed >> lane) & 1ull) != 0ull;
         const uint64_t lanebit = 1ull << lane;
 
         uint32_t staged = 0;
@@ -286,7 +295,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
             const int cnt = hi - chunk < 64 ? (int)(hi - chunk) : 64;
             for (int s = 0; s < cnt; ++s) {
                 const uint64_t S = read_lane64(mine, s);
-                const bool feas = lane_feasible(S, Aj, lane, n, k);
+                const bool feas = lane_feasible(S, Aj, lane, n, k) && lane_allowed;
                 const uint64_t fmask = ballot(feas);
                 feasible += (uint64_t)__popcll(fmask);
                 if (fmask == 0)

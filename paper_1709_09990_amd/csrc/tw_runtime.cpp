@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
@@ -16,6 +17,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "tw.h"
@@ -269,6 +271,150 @@ int fill_in_width(const Graph &g, const int32_t *order)
 // the level loop
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// §3.1, first two optimisations: clique skip and disjoint-path edges
+// ---------------------------------------------------------------------------
+
+struct Reduction {
+    uint64_t clique = 0;  // a maximum clique: never added to a state
+    int clique_size = 0;
+    // paths[u * 64 + v]: internally vertex-disjoint u-v paths for non-adjacent
+    // u, v (capped at 255); pairs that cannot reach floor + 1 are left at 0
+    std::vector<uint8_t> paths = std::vector<uint8_t>(64 * 64, 0);
+};
+
+// Bron-Kerbosch with pivoting lists every maximal clique; keep the largest,
+// ties to the one whose ascending vertex list is lexicographically smallest
+// (the lowest vertex where two equal-size sets differ lies in the smaller).
+void clique_search(const Graph &g, uint64_t R, uint64_t P, uint64_t X, uint64_t &best, int &best_size)
+{
+    if (!P && !X) {
+        const int sz = __builtin_popcountll(R);
+        const uint64_t d = R ^ best;
+        if (sz > best_size || (sz == best_size && d && (R & d & (~d + 1ull)))) {
+            best = R;
+            best_size = sz;
+        }
+        return;
+    }
+    if (__builtin_popcountll(R) + __builtin_popcountll(P) < best_size)
+        return;
+    int pivot = -1, pivot_deg = -1;
+    for (uint64_t m = P | X; m; m &= m - 1) {
+        const int u = __builtin_ctzll(m);
+        const int d = __builtin_popcountll(P & g.rows[u]);
+        if (d > pivot_deg) {
+            pivot = u;
+            pivot_deg = d;
+        }
+    }
+    for (uint64_t m = P & ~g.rows[pivot]; m; m &= m - 1) {
+        const int v = __builtin_ctzll(m);
+        const uint64_t bit = 1ull << v;
+        clique_search(g, R | bit, P & g.rows[v], X & g.rows[v], best, best_size);
+        P &= ~bit;
+        X |= bit;
+    }
+}
+
+// Menger count for non-adjacent s, t by augmenting paths in the split graph:
+// vertex w becomes in(w) -> out(w) of capacity 1 (unbounded for s and t), an
+// edge {a, b} the arcs out(a) -> in(b) and out(b) -> in(a).  Stops at `cap`.
+int vertex_disjoint_paths(const Graph &g, int s, int t, int cap)
+{
+    const int n = g.n;
+    uint8_t fv[64] = {};           // flow through in(w) -> out(w)
+    uint64_t fe[64] = {};          // fe[a] bit b: one unit on out(a) -> in(b)
+    int flow = 0;
+    int prev[128];
+    int queue[128];
+    while (flow < cap) {
+        for (int x = 0; x < 2 * n; ++x)
+            prev[x] = -2;
+        const int src = 2 * s + 1, snk = 2 * t;
+        prev[src] = -1;
+        int qh = 0, qt = 0;
+        queue[qt++] = src;
+        while (qh < qt && prev[snk] == -2) {
+            const int x = queue[qh++];
+            const int w = x >> 1;
+            auto visit = [&](int y) {
+                if (prev[y] == -2) {
+                    prev[y] = x;
+                    queue[qt++] = y;
+                }
+            };
+            if (x & 1) {  // out(w): forward to in(b) for every neighbour; back to in(w) if w carries flow
+                for (uint64_t m = g.rows[w]; m; m &= m - 1)
+                    visit(2 * __builtin_ctzll(m));
+                if (fv[w])
+                    visit(2 * w);
+            } else {      // in(w): through w if it has room; back along out(a) -> in(w) arcs with flow
+                if (w == s || w == t || !fv[w])
+                    visit(2 * w + 1);
+                for (uint64_t m = g.rows[w]; m; m &= m - 1) {
+                    const int a = __builtin_ctzll(m);
+                    if ((fe[a] >> w) & 1ull)
+                        visit(2 * a + 1);
+                }
+            }
+        }
+        if (prev[snk] == -2)
+            break;
+        for (int y = snk; prev[y] >= 0; y = prev[y]) {
+            const int x = prev[y];
+            const int wx = x >> 1, wy = y >> 1;
+            if (wx == wy) {
+                if (wx != s && wx != t)
+                    fv[wx] = (x & 1) ? 0 : 1;  // in -> out adds flow, out -> in removes it
+            } else if (x & 1) {
+                fe[wx] |= 1ull << wy;          // out(a) -> in(b)
+            } else {
+                fe[wy] &= ~(1ull << wx);       // in(b) -> out(a): cancel a unit on out(a) -> in(b)
+            }
+        }
+        ++flow;
+    }
+    return flow;
+}
+
+// Clique and path counts of g.  With floor >= 0 only bounds k >= floor will
+// be searched (and none below |C| - 1), so pairs that cannot have more paths
+// than that are skipped; floor < 0 counts every pair.
+Reduction reduction_of(const Graph &g, int floor)
+{
+    Reduction r;
+    const uint64_t all = g.n == 64 ? ~0ull : ((1ull << g.n) - 1);
+    clique_search(g, 0, all, 0, r.clique, r.clique_size);
+    if (floor >= 0)
+        floor = std::max(floor, r.clique_size - 1);
+    int deg[64];
+    for (int v = 0; v < g.n; ++v)
+        deg[v] = __builtin_popcountll(g.rows[v]);
+    for (int u = 0; u < g.n; ++u)
+        for (int v = u + 1; v < g.n; ++v) {
+            if ((g.rows[u] >> v) & 1ull)
+                continue;
+            const int bound = std::min(deg[u], deg[v]);
+            if (bound <= floor)
+                continue;  // at most `bound` paths: never reaches floor + 1
+            const int p = std::min(255, vertex_disjoint_paths(g, u, v, bound));
+            r.paths[(size_t)u * 64 + v] = r.paths[(size_t)v * 64 + u] = (uint8_t)p;
+        }
+    return r;
+}
+
+// G plus uv for every pair with >= k + 1 disjoint paths.
+Graph augmented(const Graph &g, const Reduction &r, int k)
+{
+    Graph a = g;
+    for (int u = 0; u < g.n; ++u)
+        for (int v = 0; v < g.n; ++v)
+            if ((int)r.paths[(size_t)u * 64 + v] > k)
+                a.rows[u] |= 1ull << v;
+    return a;
+}
+
 struct RunStats {
     uint64_t states_expanded = 0, expansions = 0, successors = 0, unique = 0, peak = 0;
     uint32_t decisions = 0, levels = 0, retries = 0, launches = 0;
@@ -340,18 +486,27 @@ tw_status emit_level(tw_ctx *c, const Sink &sink, int k, int i, const Level &lv,
     return TW_OK;
 }
 
-// Runs decide(k).  With keep_levels, levels[0..L] stay on the device (each
-// trimmed to its exact size) for order reconstruction; otherwise only the
-// current pair is held and levels.back() is the last level reached.  With
+// Level retention of run_decide.
+enum Keep {
+    kKeepPair = 0,     // only the current pair; levels.back() is the last level reached
+    kKeepAll = 1,      // levels[0..L] stay on the device, each trimmed to its exact size
+    kKeepIfSmall = 2,  // as kKeepAll while the kept levels fit kKeepBudget bytes, then as kKeepPair
+};
+constexpr uint64_t kKeepBudget = 1ull << 30;
+
+// Runs decide(k).  Levels are retained as `keep` says (levels.size() == L + 1
+// after a YES means every level was kept, for order reconstruction).  With
 // allowed != all, only vertices of `allowed` are ever added: the levels are
 // then the full levels restricted to subsets of `allowed` (feasibility of a
 // set does not depend on the vertices outside it being allowed).
-tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const Sink *sink,
+tw_status run_decide(tw_ctx *c, const Graph &g, int k, int keep, const Sink *sink,
                      std::vector<Level> &levels, int *yes, RunStats &rs, uint64_t allowed = ~0ull)
 {
     const int n = g.n;
     const int L = std::max(0, n - k - 1);
     const int kb = n <= 32 ? 4 : 8;
+    bool keep_levels = keep != kKeepPair;
+    uint64_t kept_bytes = 0;
     rs.decisions++;
 
     for (Level &lv : levels) {
@@ -607,6 +762,18 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, bool keep_levels, const S
         growth = in_count ? (double)out_count / (double)in_count : 1.0;
         pair_ratio = in_count ? (double)succ / (double)in_count : (double)n;
 
+        if (keep_levels && keep == kKeepIfSmall) {
+            kept_bytes += out_count * (uint64_t)(kb + 1);
+            if (kept_bytes > kKeepBudget) {
+                // too large to keep every level: continue with the current pair only
+                keep_levels = false;
+                for (size_t t = 0; t + 1 < levels.size(); ++t) {
+                    release(c, levels[t].keys);
+                    release(c, levels[t].lastv);
+                }
+                levels.erase(levels.begin(), levels.end() - 1);
+            }
+        }
         // the new level: an exact-size copy when levels are kept, else the scratch pair itself
         Level nl;
         nl.count = out_count;
@@ -740,12 +907,29 @@ void free_levels(tw_ctx *c, std::vector<Level> &levels)
     levels.clear();
 }
 
+// decide(k) with the reductions of §3.1 when red is set: NO without a search
+// below the clique bound, else the search on G_k+ never adding a clique vertex.
+tw_status run_decide_reduced(tw_ctx *c, const Graph &g, const Reduction *red, int k, int keep,
+                             const Sink *sink, std::vector<Level> &levels, int *yes, RunStats &rs,
+                             uint64_t allowed = ~0ull)
+{
+    if (!red)
+        return run_decide(c, g, k, keep, sink, levels, yes, rs, allowed);
+    if (k < red->clique_size - 1) {
+        free_levels(c, levels);
+        rs.decisions++;
+        *yes = 0;
+        return TW_OK;
+    }
+    return run_decide(c, augmented(g, *red, k), k, keep, sink, levels, yes, rs, allowed & ~red->clique);
+}
+
 // Search from bound k0 (lb <= k0 <= n-1): after a YES at k (its order kept)
 // move down, after a NO move up, until a YES at t meets a NO at t-1 or t = lb.
 // With k0 = lb this is the ascending search of Listing 1 started at the
 // minor-min-width bound.
-tw_status solve_one(tw_ctx *c, const Graph &g, int lb, int k0, int32_t *out_tw, int32_t *out_order,
-                    RunStats &rs, GraphOutcome *oc)
+tw_status solve_one(tw_ctx *c, const Graph &g, const Reduction *red, int lb, int k0, int32_t *out_tw,
+                    int32_t *out_order, RunStats &rs, GraphOutcome *oc)
 {
     const int n = g.n;
     const uint64_t e0 = rs.expansions, s0 = rs.states_expanded;
@@ -762,18 +946,19 @@ tw_status solve_one(tw_ctx *c, const Graph &g, int lb, int k0, int32_t *out_tw, 
     std::vector<Level> levels;
     while (best_yes > known_no + 1) {
         int yes = 0;
-        tw_status s = run_decide(c, g, k, false, nullptr, levels, &yes, rs);
+        tw_status s = run_decide_reduced(c, g, red, k, kKeepIfSmall, nullptr, levels, &yes, rs);
         if (s != TW_OK) {
             free_levels(c, levels);
             return s;
         }
         if (yes) {
             const uint64_t peak = rs.run_peak;
-            // the order: pick one state S_L of the last level and search again
-            // over subsets of S_L only (small), keeping those levels
+            // the order: from the kept levels, or, when they were too large to
+            // keep, pick one state S_L of the last level and search again over
+            // subsets of S_L only (small), keeping those levels
             uint64_t SL = 0;
             const int L = std::max(0, n - k - 1);
-            if (L > 0) {
+            if (L > 0 && (int)levels.size() != L + 1) {
                 const int kb = n <= 32 ? 4 : 8;
                 HIP_TRY(c, hipMemcpyAsync(&SL, levels.back().keys.p, kb, hipMemcpyDeviceToHost, c->stream));
                 HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -781,7 +966,7 @@ tw_status solve_one(tw_ctx *c, const Graph &g, int lb, int k0, int32_t *out_tw, 
                 int yes2 = 0;
                 const int dedup = c->opt.dedup;
                 c->opt.dedup = TW_DEDUP_EXACT;  // the small restricted search is always exact
-                s = run_decide(c, g, k, true, nullptr, levels, &yes2, rs, SL);
+                s = run_decide_reduced(c, g, red, k, kKeepAll, nullptr, levels, &yes2, rs, SL);
                 c->opt.dedup = dedup;
                 if (s == TW_OK && !yes2)
                     s = fail(c, TW_EDEVICE, "restricted search lost the state it started from");
@@ -790,7 +975,7 @@ tw_status solve_one(tw_ctx *c, const Graph &g, int lb, int k0, int32_t *out_tw, 
                     return s;
                 }
             }
-            s = reconstruct(c, g, k, levels, order.data());
+            s = reconstruct(c, red ? augmented(g, *red, k) : g, k, levels, order.data());
             free_levels(c, levels);
             rs.run_peak = peak;
             if (s != TW_OK)
@@ -826,7 +1011,8 @@ tw_status solve_one(tw_ctx *c, const Graph &g, int lb, int k0, int32_t *out_tw, 
 // arena of arena[t] states for graph ids[t].  Graphs that finish get their
 // tw, order and outcome; graphs whose arena or table filled up are appended
 // to single_ids for the tw_solve path.
-tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<int> &lbs,
+tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<Reduction> *reds,
+                       const std::vector<int> &lbs,
                        const std::vector<int> &k0s, const std::vector<uint64_t> &arenas,
                        const std::vector<int> &ids, int32_t *out_tw, int32_t *out_orders,
                        const std::vector<size_t> &offs, tw_status *out_status, std::vector<int> &single_ids,
@@ -851,8 +1037,9 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
         slot_total += slots[b];
     }
     const size_t job_bytes = (job_cap * sizeof(twk::BatchJob) + 15) / 16 * 16;
-    Buf d_graphs, d_jobs, d_q, d_keys, d_lastv, d_table;
+    Buf d_graphs, d_jobs, d_q, d_keys, d_lastv, d_table, d_paths;
     auto cleanup = [&]() {
+        release(c, d_paths);
         release(c, d_graphs);
         release(c, d_jobs);
         release(c, d_q);
@@ -871,10 +1058,13 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
         s = acquire(c, d_lastv, arena_total);
     if (s == TW_OK)
         s = acquire(c, d_table, slot_total * sizeof(uint64_t));
+    if (s == TW_OK && reds)
+        s = acquire(c, d_paths, B * 64 * 64);
     if (s != TW_OK) {
         cleanup();
         return s;
     }
+    std::vector<uint8_t> hpaths(reds ? B * 64 * 64 : 0);
     std::vector<twk::BatchGraph> hg(B);
     std::vector<twk::BatchJob> hj(B);
     for (size_t b = 0; b < B; ++b) {
@@ -905,6 +1095,14 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
         G.peak_yes = 1;
         for (int v = 0; v < 64; ++v)
             G.order[v] = v < g.n ? v : -1;
+        G.allowed = ~0ull;
+        G.paths = nullptr;
+        if (reds) {
+            const Reduction &r = (*reds)[(size_t)t];
+            G.allowed = ~r.clique;
+            std::memcpy(hpaths.data() + b * 64 * 64, r.paths.data(), 64 * 64);
+            G.paths = (const uint8_t *)d_paths.p + b * 64 * 64;
+        }
         twk::BatchJob &J = hj[b];
         std::memset(&J, 0, sizeof J);
         J.graph = (int32_t)b;
@@ -921,6 +1119,8 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
     HIP_TRY(c, twk::launch_fill_zero(d_jobs.p, job_bytes, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d_graphs.p, hg.data(), B * sizeof(twk::BatchGraph), hipMemcpyHostToDevice,
                               c->stream));
+    if (reds)
+        HIP_TRY(c, hipMemcpyAsync(d_paths.p, hpaths.data(), B * 64 * 64, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d_jobs.p, hj.data(), B * sizeof(twk::BatchJob), hipMemcpyHostToDevice,
                               c->stream));
     HIP_TRY(c, hipMemcpyAsync(d_q.p, &hq, sizeof hq, hipMemcpyHostToDevice, c->stream));
@@ -989,7 +1189,8 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
 }
 
 // Splits the batchable graphs into launches that fit a device-memory budget.
-tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<int> &lbs,
+tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<Reduction> *reds,
+                    const std::vector<int> &lbs,
                     const std::vector<int> &k0s, const std::vector<uint64_t> &arena_of,
                     const std::vector<int> &ids, int32_t *out_tw, int32_t *out_orders,
                     const std::vector<size_t> &offs, tw_status *out_status, std::vector<int> &single_ids,
@@ -1007,8 +1208,8 @@ tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vect
         if (q < ids.size())
             need = arena_of[(size_t)ids[q]] * 9 + arena_of[(size_t)ids[q]] * 8 + 4096;
         if (q == ids.size() || (!group.empty() && used + need > budget)) {
-            tw_status s = batch_launch(c, graphs, lbs, k0s, arenas, group, out_tw, out_orders, offs, out_status,
-                                       single_ids, outcomes, rs);
+            tw_status s = batch_launch(c, graphs, reds, lbs, k0s, arenas, group, out_tw, out_orders, offs,
+                                       out_status, single_ids, outcomes, rs);
             if (s != TW_OK)
                 return s;
             group.clear();
@@ -1123,7 +1324,8 @@ tw_status tw_ctx_create(const tw_options *options, tw_ctx **out)
         std::memcpy(&c->opt, options, sz);
     }
     c->opt.struct_size = sizeof(tw_options);
-    if (c->opt.dedup != TW_DEDUP_EXACT && c->opt.dedup != TW_DEDUP_BLOOM) {
+    if ((c->opt.dedup != TW_DEDUP_EXACT && c->opt.dedup != TW_DEDUP_BLOOM) ||
+        (c->opt.reductions != TW_REDUCE_NONE && c->opt.reductions != TW_REDUCE_CLIQUE_PATHS)) {
         delete c;
         return TW_EINVAL;
     }
@@ -1222,7 +1424,10 @@ tw_status tw_decide(tw_ctx *c, const tw_graph *gr, int32_t k, int32_t *out_yes, 
     RunStats rs;
     std::vector<Level> levels;
     int yes = 0;
-    s = run_decide(c, g, k, false, nullptr, levels, &yes, rs);
+    Reduction red;
+    if (c->opt.reductions)
+        red = reduction_of(g, -1);
+    s = run_decide_reduced(c, g, c->opt.reductions ? &red : nullptr, k, kKeepPair, nullptr, levels, &yes, rs);
     free_levels(c, levels);
     if (s != TW_OK)
         return s;
@@ -1251,7 +1456,10 @@ tw_status tw_trace_decide(tw_ctx *c, const tw_graph *gr, int32_t k,
     sk.fn = sink;
     sk.user = user;
     int yes = 0;
-    s = run_decide(c, g, k, false, &sk, levels, &yes, rs);
+    Reduction red;
+    if (c->opt.reductions)
+        red = reduction_of(g, -1);
+    s = run_decide_reduced(c, g, c->opt.reductions ? &red : nullptr, k, kKeepPair, &sk, levels, &yes, rs);
     free_levels(c, levels);
     if (s != TW_OK)
         return s;
@@ -1273,7 +1481,12 @@ tw_status tw_solve(tw_ctx *c, const tw_graph *gr, int32_t *out_tw, int32_t *out_
         return fail(c, TW_EDEVICE, "hipSetDevice failed");
     const double t0 = now_s();
     RunStats rs;
-    const int lb = mmw_bound(g);
+    int lb = mmw_bound(g);
+    Reduction red;
+    if (c->opt.reductions) {
+        red = reduction_of(g, lb);
+        lb = std::max(lb, red.clique_size - 1);
+    }
     std::vector<Graph> one(1, g);
     std::vector<int> lbs(1, lb), k0s(1, lb), ids(1, 0);
     std::vector<uint64_t> arena(1, 0);
@@ -1282,7 +1495,7 @@ tw_status tw_solve(tw_ctx *c, const tw_graph *gr, int32_t *out_tw, int32_t *out_
         if (s != TW_OK)
             return s;
     }
-    s = solve_one(c, g, lb, k0s[0], out_tw, out_order, rs, nullptr);
+    s = solve_one(c, g, c->opt.reductions ? &red : nullptr, lb, k0s[0], out_tw, out_order, rs, nullptr);
     if (s != TW_OK)
         return s;
     add_stats(stats, rs, now_s() - t0);
@@ -1325,10 +1538,33 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
         off += gs[t].n;
         out_tw[t] = -1;
         out_status[t] = validate(c, &gs[t], graphs[t]);
+        if (out_status[t] == TW_OK)
+            lbs[t] = mmw_bound(graphs[t]);
+    }
+    // §3.1 reductions: clique and path counts per graph, on the host's cores
+    std::vector<Reduction> reds;
+    if (c->opt.reductions) {
+        reds.resize(count);
+        const unsigned nth = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 16u));
+        std::vector<std::thread> pool;
+        std::atomic<uint32_t> next{0};
+        for (unsigned w = 0; w < nth; ++w)
+            pool.emplace_back([&]() {
+                for (uint32_t t; (t = next.fetch_add(1)) < count;)
+                    if (out_status[t] == TW_OK)
+                        reds[t] = reduction_of(graphs[t], lbs[t]);
+            });
+        for (std::thread &th : pool)
+            th.join();
+        for (uint32_t t = 0; t < count; ++t)
+            if (out_status[t] == TW_OK)
+                lbs[t] = std::max(lbs[t], reds[t].clique_size - 1);
+    }
+    for (uint32_t t = 0; t < count; ++t) {
         if (out_status[t] != TW_OK)
             continue;
         const Graph &g = graphs[t];
-        lbs[t] = k0s[t] = mmw_bound(g);
+        k0s[t] = lbs[t];
         // an arena never needs more than every subset of V (minus V itself)
         arena_of[t] = g.n < 20 ? std::min<uint64_t>(default_arena, 1ull << g.n) : default_arena;
         if (lbs[t] >= g.n - 1) {
@@ -1364,13 +1600,15 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
         }
         batch_ids.swap(keep);
     }
-    st = batch_run(c, graphs, lbs, k0s, arena_of, batch_ids, out_tw, out_orders, offs, out_status, single_ids,
-                   outcomes, rs);
+    const std::vector<Reduction> *rp = c->opt.reductions ? &reds : nullptr;
+    st = batch_run(c, graphs, rp, lbs, k0s, arena_of, batch_ids, out_tw, out_orders, offs, out_status,
+                   single_ids, outcomes, rs);
     if (st != TW_OK)
         return st;
     for (int t : single_ids) {
         GraphOutcome oc;
-        tw_status s = solve_one(c, graphs[(size_t)t], lbs[(size_t)t], k0s[(size_t)t], &out_tw[t],
+        tw_status s = solve_one(c, graphs[(size_t)t], rp ? &reds[(size_t)t] : nullptr, lbs[(size_t)t],
+                                k0s[(size_t)t], &out_tw[t],
                                 out_orders + offs[(size_t)t], rs, &oc);
         out_status[t] = s;
         if (s != TW_OK)
@@ -1444,6 +1682,23 @@ out:
         (void)hipFree(sink);
     (void)hipFree(buf);
     return st;
+}
+
+tw_status tw_reductions(const tw_graph *gr, uint64_t *out_clique, uint8_t *out_paths)
+{
+    if (!out_clique)
+        return TW_EINVAL;
+    Graph g;
+    tw_status s = validate(nullptr, gr, g);
+    if (s != TW_OK)
+        return s;
+    const Reduction r = reduction_of(g, -1);
+    *out_clique = r.clique;
+    if (out_paths)
+        for (int u = 0; u < g.n; ++u)
+            for (int v = 0; v < g.n; ++v)
+                out_paths[u * g.n + v] = r.paths[(size_t)u * 64 + v];
+    return TW_OK;
 }
 
 tw_status tw_mmw(const tw_graph *gr, int32_t *out_lb)

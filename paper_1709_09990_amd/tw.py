@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libtw.so")
 TW_OK, TW_EINVAL, TW_ENOMEM, TW_EDEVICE, TW_ECAPACITY = range(5)
 TW_DEDUP_EXACT, TW_DEDUP_BLOOM = 0, 1
 TW_K_ASCENDING, TW_K_LEARNED = 0, 1
+TW_REDUCE_NONE, TW_REDUCE_CLIQUE_PATHS = 0, 1
 
 
 class TwError(RuntimeError):
@@ -46,6 +47,7 @@ class _Options(ctypes.Structure):
         ("partition", ctypes.c_int),
         ("batch_graph_states", ctypes.c_uint64),
         ("batch_chunk", ctypes.c_uint32),
+        ("reductions", ctypes.c_int),
     ]
 
 
@@ -97,7 +99,7 @@ EXPORTS = (
     "tw_trace_decide", "tw_mmw", "tw_order_width", "tw_status_str", "tw_last_error",
     "tw_mpnn_param_count", "tw_mpnn_features", "tw_mpnn_create", "tw_mpnn_destroy",
     "tw_mpnn_set_params", "tw_mpnn_get_params", "tw_mpnn_predict", "tw_mpnn_gradients",
-    "tw_mpnn_train_step", "tw_probe_rate",
+    "tw_mpnn_train_step", "tw_probe_rate", "tw_reductions",
 )
 
 _lib = None
@@ -124,6 +126,7 @@ def load():
                                   P(ctypes.c_int32)]
     L.tw_mmw.argtypes = [P(_Graph), P(ctypes.c_int32)]
     L.tw_order_width.argtypes = [P(_Graph), P(ctypes.c_int32), P(ctypes.c_int32)]
+    L.tw_reductions.argtypes = [P(_Graph), P(ctypes.c_uint64), P(ctypes.c_uint8)]
     L.tw_probe_rate.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
                                 P(ctypes.c_double)]
     L.tw_status_str.argtypes = [ctypes.c_int]
@@ -146,7 +149,7 @@ def load():
     for name in ("tw_ctx_create", "tw_decide", "tw_solve", "tw_solve_batch", "tw_trace_decide",
                  "tw_mmw", "tw_order_width", "tw_mpnn_features", "tw_mpnn_create", "tw_mpnn_set_params",
                  "tw_mpnn_get_params", "tw_mpnn_predict", "tw_mpnn_gradients", "tw_mpnn_train_step",
-                 "tw_probe_rate"):
+                 "tw_probe_rate", "tw_reductions"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -170,6 +173,19 @@ def mmw(rows) -> int:
     if st != TW_OK:
         raise TwError(st, L.tw_status_str(st).decode())
     return out.value
+
+
+def reductions(rows) -> tuple[list[int], np.ndarray]:
+    """(maximum clique skipped by TW_REDUCE_CLIQUE_PATHS, n x n disjoint-path counts)."""
+    L = load()
+    g, keep = _graph(rows)
+    n = len(keep)
+    clique = ctypes.c_uint64(0)
+    paths = np.zeros(n * n, dtype=np.uint8)
+    st = L.tw_reductions(ctypes.byref(g), ctypes.byref(clique), paths.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    if st != TW_OK:
+        raise TwError(st, L.tw_status_str(st).decode())
+    return [v for v in range(n) if (clique.value >> v) & 1], paths.reshape(n, n)
 
 
 def order_width(rows, order) -> int:
@@ -213,7 +229,8 @@ class Context:
     def __init__(self, device: int = 0, stream=None, dedup: int = TW_DEDUP_EXACT,
                  load_factor: float = 0.0, max_states: int = 0, capacity_override: int = 0,
                  timing: bool = False, k_policy: int = TW_K_ASCENDING, weights_path: str | None = None,
-                 batch_graph_states: int = 0, batch_chunk: int = 0, probe: int = 0, partition: int = 0):
+                 batch_graph_states: int = 0, batch_chunk: int = 0, probe: int = 0, partition: int = 0,
+                 reductions: int = TW_REDUCE_NONE):
         L = load()
         self._L = L
         o = _Options()
@@ -232,6 +249,7 @@ class Context:
         o.partition = partition
         o.batch_graph_states = batch_graph_states
         o.batch_chunk = batch_chunk
+        o.reductions = reductions
         h = ctypes.c_void_p()
         st = L.tw_ctx_create(ctypes.byref(o), ctypes.byref(h))
         if st != TW_OK:

@@ -84,3 +84,21 @@ def test_network_features_match_reference():
         got = T.mpnn_features(rows)
         assert np.allclose(got, X[:, :4].astype(np.float32))
     assert T.mpnn_param_count() == M.N_PARAMS
+
+
+def test_reductions_match_oracle():
+    """Host prep of the §3.1 reductions (clique, disjoint-path counts) equals
+    the oracle's independent implementation."""
+    from oracle import reductions as R
+    rng = random.Random(23)
+    graphs = [G.grid(4, 5), G.petersen(), G.cycle(11), G.complete(6), G.edgeless(4),
+              G.complete_bipartite(3, 6), G.complete_multipartite([2, 3, 4]), G.disjoint_cliques(3, 3)]
+    graphs += [G.gnp(rng.randint(8, 24), rng.choice([0.15, 0.3, 0.5]), 1200 + s) for s in range(16)]
+    graphs += [G.partial_ktree(rng.randint(10, 26), rng.randint(3, 7), 0.3, 1300 + s) for s in range(8)]
+    graphs += [G.rgg(rng.randint(10, 26), 6.0, 1400 + s) for s in range(6)]
+    w = G.workload_single_n40()
+    graphs += [w["gnp40_p015"], w["partial8tree40"]]
+    for rows in graphs:
+        clique, paths = T.reductions(rows)
+        assert clique == R.max_clique(rows)
+        assert np.array_equal(paths.astype(np.int32), np.minimum(R.disjoint_paths(rows), 255))
