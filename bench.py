@@ -12,8 +12,11 @@ solves and nothing else.
 
 Prints one JSON line.  Fields beyond the driver's contract:
   batch         graphs solved per second on 512 held-out graphs (n 20..32),
-                batched, plain ascending-k vs the learned start bound
+                batched: plain ascending k, the learned start bound, and both
+                with the clique skip and disjoint-path edges of §3.1
                 (outside the timed region of `value`)
+  reductions    the bench solves again with those reductions: time per step
+                and expansions against the plain Listing 1 search
   roofline      the expansion kernel against HBM bandwidth, algorithmic bytes
                 (key read per state, one compare-and-swap per feasible pair,
                 key + creator byte written per new state) over the kernel time
@@ -97,6 +100,8 @@ def copy_probe(nbytes: int, reps: int = 5):
 
 
 WEIGHTS = os.path.join(ROOT, "paper_1709_09990_amd", "weights", "mpnn_mixture_n16_30.bin")
+# trained on labels of the search with the §3.1 reductions (their peak levels)
+WEIGHTS_REDUCED = os.path.join(ROOT, "paper_1709_09990_amd", "weights", "mpnn_mixture_n16_30_reduced.bin")
 
 
 def probe_reference(kernel_successors_per_s: float) -> dict:
@@ -126,7 +131,11 @@ def batch_leg(count: int = 512):
     graphs = G.workload_batch(count, seed0=600000, n_lo=20, n_hi=32)
     out = {"graphs": count, "n": [20, 32], "weights": os.path.relpath(WEIGHTS, ROOT)}
     ref = None
-    for name, kw in (("plain", {}), ("learned", {"k_policy": T.TW_K_LEARNED, "weights_path": WEIGHTS})):
+    red = {"reductions": T.TW_REDUCE_CLIQUE_PATHS}
+    learned = {"k_policy": T.TW_K_LEARNED, "weights_path": WEIGHTS}
+    learned_red = {"k_policy": T.TW_K_LEARNED, "weights_path": WEIGHTS_REDUCED, **red}
+    for name, kw in (("plain", {}), ("learned", learned), ("plain_reduced", red),
+                     ("learned_reduced", learned_red)):
         with T.Context(device=0, **kw) as c:
             c.solve_batch(graphs[:16])
             t0 = time.perf_counter()
@@ -134,13 +143,42 @@ def batch_leg(count: int = 512):
             dt = time.perf_counter() - t0
         if np.any(status != 0):
             raise RuntimeError(f"batch leg: {name} failed on {int(np.sum(status != 0))} graphs")
-        ref = tws if ref is None else ref
         out[f"{name}_graphs_per_s"] = round(count / dt, 2)
         out[f"{name}_expansions"] = st["expansions"]
         out[f"{name}_bounds_tried"] = st["decisions"]
-        if name == "learned":
-            out["identical"] = bool(np.array_equal(ref, tws))
+        if ref is None:
+            ref = tws
+        elif not np.array_equal(ref, tws):
+            raise RuntimeError(f"batch leg: {name} changed an answer")
+    out["identical"] = True
     out["learned_speedup"] = round(out["learned_graphs_per_s"] / out["plain_graphs_per_s"], 3)
+    out["learned_reduced_speedup"] = round(out["learned_reduced_graphs_per_s"] /
+                                           out["plain_reduced_graphs_per_s"], 3)
+    out["weights_reduced"] = os.path.relpath(WEIGHTS_REDUCED, ROOT)
+    return out
+
+
+def reductions_leg(graphs: dict, steps: int = 2) -> dict:
+    """The same single-graph solves with the clique skip and disjoint-path
+    edges of §3.1 (TW_REDUCE_CLIQUE_PATHS): time per step and work, answers
+    checked against the plain search's."""
+    from paper_1709_09990_amd import tw as T
+    out = {}
+    with T.Context(device=0, timing=True, reductions=T.TW_REDUCE_CLIQUE_PATHS) as c:
+        for nm in graphs:
+            c.solve(graphs[nm])  # warm
+        t0 = time.perf_counter()
+        exp = 0
+        tws = {}
+        for _ in range(steps):
+            for nm in graphs:
+                tw, _, st = c.solve(graphs[nm])
+                tws[nm] = tw
+                exp += st["expansions"]
+        dt = time.perf_counter() - t0
+    out["ms_per_step"] = dt / steps * 1e3
+    out["expansions_per_step"] = exp // steps
+    out["treewidth"] = tws
     return out
 
 
@@ -189,6 +227,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched learned-vs-plain leg")
     ap.add_argument("--no-probe", action="store_true", help="skip the random-access reference measurement")
+    ap.add_argument("--no-reduce", action="store_true", help="skip the single-graph leg with the section 3.1 reductions")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -282,6 +321,13 @@ def main():
         "roofline": roofline,
     }
     ctx.close()
+    if not args.no_reduce:
+        r = reductions_leg(graphs)
+        if r["treewidth"] != tws:
+            raise RuntimeError(f"reductions changed an answer: {r['treewidth']} vs {tws}")
+        r["speedup_vs_plain_step"] = round(out["ms_per_step"] / r["ms_per_step"], 3)
+        r["expansions_plain_per_step"] = total["expansions"] // args.steps
+        out["reductions"] = r
     if not args.no_batch:
         out["batch"] = batch_leg()
     if not args.no_cpu:

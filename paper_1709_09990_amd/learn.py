@@ -8,7 +8,9 @@
    the mixture holds graphs needing 10^11 and more (S,v) pairs each, which
    makes 20,000 exact labels too costly; the range is an argument.)
 2. Labels from exact runs of the batched solver: tw, and the largest level of
-   the run that certified it.  Targets: tw/n and log2(peak+1)/32.
+   the run that certified it (with --reductions, of the search with the
+   clique skip and disjoint-path edges of §3.1).  Targets: tw/n and
+   log2(peak+1)/32.
 3. Training with the library's bf16 MFMA forward/backward kernels and AdamW.
 4. Evaluation on held-out graphs (n ~ U{20..32} by default, seeds 600000+):
    the learned start bound against the plain ascending search, both batched,
@@ -82,11 +84,11 @@ def train(net: T.Mpnn, graphs, targets, epochs: int, batch: int, lr: float, wd: 
     return history
 
 
-def evaluate(graphs, weights_path: str, log=print) -> dict:
+def evaluate(graphs, weights_path: str, log=print, reductions: int = T.TW_REDUCE_NONE) -> dict:
     """Plain ascending search vs learned start, both batched, same GPU."""
     out = {}
     for name, kw in (("plain", {}), ("learned", {"k_policy": T.TW_K_LEARNED, "weights_path": weights_path})):
-        with T.Context(device=0, **kw) as c:
+        with T.Context(device=0, reductions=reductions, **kw) as c:
             c.solve_batch(graphs[:8])  # warm the context
             t0 = time.perf_counter()
             tws, orders, status, st, per = c.solve_batch(graphs, graph_stats=True)
@@ -118,14 +120,19 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default="weights.bin")
     ap.add_argument("--eval-only", action="store_true", help="skip labelling and training; evaluate --out")
+    ap.add_argument("--reductions", action="store_true",
+                    help="label, and evaluate, with the clique skip and disjoint-path edges of section 3.1 "
+                         "(the peak label is then the reduced search's)")
     args = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
 
+    red = T.TW_REDUCE_CLIQUE_PATHS if args.reductions else T.TW_REDUCE_NONE
+
     if args.eval_only:
         ev = make_graphs(args.eval, 600000, *args.eval_n)
-        res = evaluate(ev, args.out, log=log)
+        res = evaluate(ev, args.out, log=log, reductions=red)
         log(f"identical answers: {res['identical']}; speedup "
             f"{res['learned']['graphs_per_s'] / res['plain']['graphs_per_s']:.3f}x")
         return 0
@@ -137,7 +144,7 @@ def main(argv=None):
         tws, peaks = z["tw"], z["peak"]
         log(f"labels from {cache}")
     else:
-        with T.Context(device=0) as ctx:
+        with T.Context(device=0, reductions=red) as ctx:
             tws, peaks = label(graphs, ctx, log=log)
         np.savez(cache, tw=tws, peak=peaks)
     targets = targets_of(graphs, tws, peaks)
@@ -150,7 +157,7 @@ def main(argv=None):
     log(f"train: start bound exact for {np.mean(err == 0):.3f}, within 1 for {np.mean(err <= 1):.3f}")
     if args.eval:
         ev = make_graphs(args.eval, 600000, *args.eval_n)
-        res = evaluate(ev, args.out, log=log)
+        res = evaluate(ev, args.out, log=log, reductions=red)
         log(f"identical answers: {res['identical']}; speedup "
             f"{res['learned']['graphs_per_s'] / res['plain']['graphs_per_s']:.3f}x")
     return 0

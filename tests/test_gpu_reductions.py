@@ -129,3 +129,20 @@ def test_reduced_full_size_bench_graphs(oracle):
             tw, order, st = r.solve(w[name])
             assert tw == tw_want
             assert oracle.order_width(w[name], order) == tw
+
+
+def test_learned_start_with_reductions_is_exact(oracle):
+    """The network trained on reduced-search labels only moves the start bound
+    and admission: answers equal the oracle's, orders have that width."""
+    import os
+    from paper_1709_09990_amd import tw as T
+    w = os.path.join(os.path.dirname(T.__file__), "weights", "mpnn_mixture_n16_30_reduced.bin")
+    graphs = G.workload_batch(48, seed0=7700, n_lo=16, n_hi=30)
+    want = [oracle.treewidth_bfs(r, oracle.mmw(r)) for r in graphs]
+    with T.Context(device=0, reductions=T.TW_REDUCE_CLIQUE_PATHS, k_policy=T.TW_K_LEARNED, weights_path=w) as c:
+        tws, orders, status, _ = c.solve_batch(graphs)
+        assert list(status) == [0] * len(graphs) and list(tws) == want
+        for rows, tw, order in zip(graphs, tws, orders):
+            assert oracle.order_width(rows, order) == tw
+        for rows, tw in zip(graphs[:6], want[:6]):
+            assert c.solve(rows)[0] == tw
