@@ -203,6 +203,18 @@ tw_status tw_mmw(const tw_graph *g, int32_t *out_lb);
  * non-adjacent u != v, capped at 255, 0 on the diagonal and for edges. */
 tw_status tw_reductions(const tw_graph *g, uint64_t *out_clique, uint8_t *out_paths);
 
+/* Tree decomposition from an elimination order (§1 states the goal is a
+ * decomposition; §2 gives the order view).  Eliminating the vertices in order
+ * with fill-in, bag(v) = v plus its neighbours not yet eliminated at that time;
+ * out_bags[v] (n masks) holds it, and out_parent[v] (n entries) is the vertex
+ * of bag(v) minus v that is eliminated first, or -1 when that set is empty
+ * (one root per connected component).  These bags on that forest satisfy the
+ * three conditions of a tree decomposition, and *out_width = max |bag| - 1 is
+ * the order's width.  TW_EINVAL if order is not a permutation of 0..n-1.
+ * Host only; all arrays caller-owned. */
+tw_status tw_tree_decomposition(const tw_graph *g, const int32_t *order, uint64_t *out_bags,
+                                int32_t *out_parent, int32_t *out_width);
+
 /* Width of an elimination order by fill-in (§2); -1 in *out_width if order is
  * not a permutation of 0..n-1.  Host only. */
 tw_status tw_order_width(const tw_graph *g, const int32_t *order, int32_t *out_width);

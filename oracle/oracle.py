@@ -351,3 +351,46 @@ def set_hashes(states: np.ndarray) -> tuple[int, int, int]:
         tot = int(np.add.reduce(_mix_a(s), dtype=np.uint64))
     x = int(np.bitwise_xor.reduce(_mix_b(s)))
     return len(s), tot, x
+
+
+# ---------------------------------------------------------------------------
+# tree decompositions (§1: the goal the treewidth search serves)
+# ---------------------------------------------------------------------------
+
+def is_tree_decomposition(rows, bags, parent) -> bool:
+    """The three conditions of a tree decomposition, for bags (vertex masks)
+    hung on the forest given by parent (-1 = root), checked as defined:
+    every vertex and every edge lies in some bag, and for every vertex the
+    bags holding it form one connected subtree (exactly one of them has a
+    parent bag that does not hold it, or no parent)."""
+    a = [int(r) for r in rows]
+    n = len(a)
+    m = len(bags)
+    if len(parent) != m:
+        return False
+    # parent pointers must form a forest: walking up always reaches a root
+    for b in range(m):
+        seen = set()
+        x = b
+        while x != -1:
+            if x in seen or not (-1 <= parent[x] < m):
+                return False
+            seen.add(x)
+            x = parent[x]
+    bag_sets = [{v for v in range(n) if (int(bags[b]) >> v) & 1} for b in range(m)]
+    for v in range(n):
+        holding = [b for b in range(m) if v in bag_sets[b]]
+        if not holding:
+            return False
+        tops = [b for b in holding if parent[b] == -1 or v not in bag_sets[parent[b]]]
+        if len(tops) != 1:
+            return False
+    for u in range(n):
+        for v in range(u + 1, n):
+            if (a[u] >> v) & 1 and not any(u in s and v in s for s in bag_sets):
+                return False
+    return True
+
+
+def decomposition_width(bags) -> int:
+    return max(bin(int(b)).count("1") for b in bags) - 1 if len(bags) else -1

@@ -1713,6 +1713,50 @@ tw_status tw_mmw(const tw_graph *gr, int32_t *out_lb)
     return TW_OK;
 }
 
+tw_status tw_tree_decomposition(const tw_graph *gr, const int32_t *order, uint64_t *out_bags,
+                                int32_t *out_parent, int32_t *out_width)
+{
+    if (!order || !out_bags || !out_parent || !out_width)
+        return TW_EINVAL;
+    Graph g;
+    tw_status s = validate(nullptr, gr, g);
+    if (s != TW_OK)
+        return s;
+    int pos[64];
+    uint64_t seen = 0;
+    for (int t = 0; t < g.n; ++t) {
+        const int v = order[t];
+        if (v < 0 || v >= g.n || ((seen >> v) & 1ull))
+            return TW_EINVAL;
+        seen |= 1ull << v;
+        pos[v] = t;
+    }
+    // eliminate in order; bag(v) = v plus its neighbours still present, which
+    // become a clique (fill-in); the parent is the one of them eliminated first
+    uint64_t adj[64];
+    for (int v = 0; v < g.n; ++v)
+        adj[v] = g.rows[v];
+    uint64_t alive = seen;
+    int width = 0;
+    for (int t = 0; t < g.n; ++t) {
+        const int v = order[t];
+        const uint64_t N = adj[v] & alive & ~(1ull << v);
+        width = std::max(width, popc(N));
+        out_bags[v] = N | (1ull << v);
+        int parent = -1;
+        for (uint64_t a = N; a; a &= a - 1) {
+            const int u = __builtin_ctzll(a);
+            adj[u] |= N & ~(1ull << u);
+            if (parent < 0 || pos[u] < pos[parent])
+                parent = u;
+        }
+        out_parent[v] = parent;
+        alive &= ~(1ull << v);
+    }
+    *out_width = width;
+    return TW_OK;
+}
+
 tw_status tw_order_width(const tw_graph *gr, const int32_t *order, int32_t *out_width)
 {
     if (!order || !out_width)

@@ -99,7 +99,7 @@ EXPORTS = (
     "tw_trace_decide", "tw_mmw", "tw_order_width", "tw_status_str", "tw_last_error",
     "tw_mpnn_param_count", "tw_mpnn_features", "tw_mpnn_create", "tw_mpnn_destroy",
     "tw_mpnn_set_params", "tw_mpnn_get_params", "tw_mpnn_predict", "tw_mpnn_gradients",
-    "tw_mpnn_train_step", "tw_probe_rate", "tw_reductions",
+    "tw_mpnn_train_step", "tw_probe_rate", "tw_reductions", "tw_tree_decomposition",
 )
 
 _lib = None
@@ -126,6 +126,8 @@ def load():
                                   P(ctypes.c_int32)]
     L.tw_mmw.argtypes = [P(_Graph), P(ctypes.c_int32)]
     L.tw_order_width.argtypes = [P(_Graph), P(ctypes.c_int32), P(ctypes.c_int32)]
+    L.tw_tree_decomposition.argtypes = [P(_Graph), P(ctypes.c_int32), P(ctypes.c_uint64), P(ctypes.c_int32),
+                                        P(ctypes.c_int32)]
     L.tw_reductions.argtypes = [P(_Graph), P(ctypes.c_uint64), P(ctypes.c_uint8)]
     L.tw_probe_rate.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
                                 P(ctypes.c_double)]
@@ -149,7 +151,7 @@ def load():
     for name in ("tw_ctx_create", "tw_decide", "tw_solve", "tw_solve_batch", "tw_trace_decide",
                  "tw_mmw", "tw_order_width", "tw_mpnn_features", "tw_mpnn_create", "tw_mpnn_set_params",
                  "tw_mpnn_get_params", "tw_mpnn_predict", "tw_mpnn_gradients", "tw_mpnn_train_step",
-                 "tw_probe_rate", "tw_reductions"):
+                 "tw_probe_rate", "tw_reductions", "tw_tree_decomposition"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -186,6 +188,23 @@ def reductions(rows) -> tuple[list[int], np.ndarray]:
     if st != TW_OK:
         raise TwError(st, L.tw_status_str(st).decode())
     return [v for v in range(n) if (clique.value >> v) & 1], paths.reshape(n, n)
+
+
+def tree_decomposition(rows, order) -> tuple[list[int], list[int], int]:
+    """(bags as vertex masks, parent per bag or -1, width) from an elimination order."""
+    L = load()
+    g, keep = _graph(rows)
+    n = len(keep)
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    bags = np.zeros(n, dtype=np.uint64)
+    parent = np.zeros(n, dtype=np.int32)
+    width = ctypes.c_int32(0)
+    st = L.tw_tree_decomposition(ctypes.byref(g), o.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 bags.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                 parent.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(width))
+    if st != TW_OK:
+        raise TwError(st, L.tw_status_str(st).decode())
+    return [int(b) for b in bags], [int(p) for p in parent], width.value
 
 
 def order_width(rows, order) -> int:

@@ -102,3 +102,25 @@ def test_reductions_match_oracle():
         clique, paths = T.reductions(rows)
         assert clique == R.max_clique(rows)
         assert np.array_equal(paths.astype(np.int32), np.minimum(R.disjoint_paths(rows), 255))
+
+
+def test_tree_decomposition_from_orders(oracle):
+    """tw_tree_decomposition on optimal orders (oracle brute force) and on
+    random orders: a valid decomposition whose width is the order's width."""
+    rng = random.Random(31)
+    graphs = [G.petersen(), G.grid(3, 3), G.cycle(7), G.complete_bipartite(2, 4), G.disjoint_cliques(3, 2)]
+    graphs += [G.gnp(rng.randint(5, 9), 0.4, 1500 + s) for s in range(10)]
+    for rows in graphs:
+        n = len(rows)
+        tw, best = oracle.brute_force(rows)
+        bags, parent, width = T.tree_decomposition(rows, best)
+        assert width == tw == oracle.decomposition_width(bags)
+        assert oracle.is_tree_decomposition(rows, bags, parent)
+        for _ in range(5):
+            order = list(range(n))
+            rng.shuffle(order)
+            bags, parent, width = T.tree_decomposition(rows, order)
+            assert width == oracle.order_width(rows, order)
+            assert oracle.is_tree_decomposition(rows, bags, parent)
+    with pytest.raises(T.TwError):
+        T.tree_decomposition(G.path(3), [0, 0, 1])

@@ -129,6 +129,9 @@ def test_reduced_full_size_bench_graphs(oracle):
             tw, order, st = r.solve(w[name])
             assert tw == tw_want
             assert oracle.order_width(w[name], order) == tw
+            # the order's tree decomposition is valid and has width tw
+            bags, parent, width = T.tree_decomposition(w[name], order)
+            assert width == tw and oracle.is_tree_decomposition(w[name], bags, parent)
 
 
 def test_learned_start_with_reductions_is_exact(oracle):

@@ -277,3 +277,21 @@ def test_pins_catch_planted_mistakes(oracle):
             rng.shuffle(order)
             caught |= width(rows, order, bad) != oracle.order_width(rows, order)
         assert caught
+
+
+def test_tree_decomposition_checker(oracle):
+    """Hand-made decompositions: valid ones pass, each broken condition fails."""
+    P4 = G.path(4)  # 0-1-2-3
+    bags = [0b0011, 0b0110, 0b1100]
+    assert oracle.is_tree_decomposition(P4, bags, [-1, 0, 1])
+    assert oracle.decomposition_width(bags) == 1
+    assert not oracle.is_tree_decomposition(P4, [0b0011, 0b1100], [-1, 0])          # edge 1-2 uncovered
+    assert not oracle.is_tree_decomposition(P4, [0b0011, 0b0100, 0b1110], [-1, 0, 1])  # bags of 1 disconnected
+    assert not oracle.is_tree_decomposition(P4, bags, [1, 2, 0])                     # parent cycle
+    assert not oracle.is_tree_decomposition(P4, [0b0011, 0b0110], [-1, 0])           # vertex 3 missing
+    C4 = G.cycle(4)
+    assert oracle.is_tree_decomposition(C4, [0b0111, 0b1101], [-1, 0])
+    assert not oracle.is_tree_decomposition(C4, [0b0011, 0b0110, 0b1100], [-1, 0, 1])  # edge 3-0 uncovered
+    # two components: a forest with two roots
+    two = G.disjoint_cliques(2, 2)
+    assert oracle.is_tree_decomposition(two, [0b0011, 0b1100], [-1, -1])
