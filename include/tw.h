@@ -52,7 +52,10 @@ typedef enum {
 /* Duplicate removal between levels (§3.2). */
 enum {
     TW_DEDUP_EXACT = 0, /* open-addressing hash table in HBM, atomic compare-and-swap (default) */
-    TW_DEDUP_BLOOM = 1  /* Bloom filter, 17 probes by double hashing (§3.2); a NO answer is then not certified */
+    TW_DEDUP_BLOOM = 1, /* Bloom filter, 17 probes by double hashing (§3.2); a NO answer is then not certified */
+    TW_DEDUP_BLOOM_CERTIFIED = 2 /* Bloom search, and every NO of tw_decide / tw_solve decided again by the
+                                    exact search (a false positive only drops states, so only a NO can be
+                                    wrong; a YES is certified by its order's width) */
 };
 
 /* Choice of the bounds k tried by tw_solve / tw_solve_batch (§3.1). */
@@ -73,7 +76,7 @@ typedef struct {
     size_t struct_size;
     int device;               /* HIP device ordinal */
     void *stream;             /* hipStream_t to launch on, or NULL for a stream the context creates */
-    int dedup;                /* TW_DEDUP_EXACT or TW_DEDUP_BLOOM */
+    int dedup;                /* TW_DEDUP_EXACT, TW_DEDUP_BLOOM or TW_DEDUP_BLOOM_CERTIFIED */
     float load_factor;        /* target hash-table load in (0, 0.9]; 0 picks the default 0.25 (raised
                                  towards 0.5 when the table would take over a third of free memory) */
     int k_policy;             /* TW_K_ASCENDING or TW_K_LEARNED */

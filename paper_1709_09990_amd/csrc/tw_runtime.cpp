@@ -548,7 +548,7 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, int keep, const Sink *sin
     for (; i < L; ++i) {
         Level &in = levels.back();
         const uint64_t in_count = in.count;
-        const bool bloom = c->opt.dedup == TW_DEDUP_BLOOM;
+        const bool bloom = c->opt.dedup == TW_DEDUP_BLOOM || c->opt.dedup == TW_DEDUP_BLOOM_CERTIFIED;
         // every new state comes from a distinct (S, v) pair; exact dedup also
         // never exceeds C(n, i+1), while concurrent Bloom inserts of one state
         // may both report it new
@@ -924,6 +924,21 @@ tw_status run_decide_reduced(tw_ctx *c, const Graph &g, const Reduction *red, in
     return run_decide(c, augmented(g, *red, k), k, keep, sink, levels, yes, rs, allowed & ~red->clique);
 }
 
+// decide(k) as run_decide_reduced; under TW_DEDUP_BLOOM_CERTIFIED a NO of the
+// Bloom search is decided again by the exact search (a false positive of the
+// filter only drops states, so only a NO can be wrong).
+tw_status decide_checked(tw_ctx *c, const Graph &g, const Reduction *red, int k, int keep,
+                         std::vector<Level> &levels, int *yes, RunStats &rs)
+{
+    tw_status s = run_decide_reduced(c, g, red, k, keep, nullptr, levels, yes, rs);
+    if (s == TW_OK && !*yes && c->opt.dedup == TW_DEDUP_BLOOM_CERTIFIED) {
+        c->opt.dedup = TW_DEDUP_EXACT;
+        s = run_decide_reduced(c, g, red, k, keep, nullptr, levels, yes, rs);
+        c->opt.dedup = TW_DEDUP_BLOOM_CERTIFIED;
+    }
+    return s;
+}
+
 // Search from bound k0 (lb <= k0 <= n-1): after a YES at k (its order kept)
 // move down, after a NO move up, until a YES at t meets a NO at t-1 or t = lb.
 // With k0 = lb this is the ascending search of Listing 1 started at the
@@ -946,7 +961,7 @@ tw_status solve_one(tw_ctx *c, const Graph &g, const Reduction *red, int lb, int
     std::vector<Level> levels;
     while (best_yes > known_no + 1) {
         int yes = 0;
-        tw_status s = run_decide_reduced(c, g, red, k, kKeepIfSmall, nullptr, levels, &yes, rs);
+        tw_status s = decide_checked(c, g, red, k, kKeepIfSmall, levels, &yes, rs);
         if (s != TW_OK) {
             free_levels(c, levels);
             return s;
@@ -981,7 +996,7 @@ tw_status solve_one(tw_ctx *c, const Graph &g, const Reduction *red, int lb, int
             if (s != TW_OK)
                 return s;
             const int w = fill_in_width(g, order.data());
-            best_yes = (c->opt.dedup == TW_DEDUP_BLOOM && w >= lb && w < k) ? w : k;
+            best_yes = (c->opt.dedup != TW_DEDUP_EXACT && w >= lb && w < k) ? w : k;
             peak_yes = rs.run_peak;
             std::copy(order.begin(), order.end(), out_order);
             k = best_yes - 1;
@@ -1324,7 +1339,8 @@ tw_status tw_ctx_create(const tw_options *options, tw_ctx **out)
         std::memcpy(&c->opt, options, sz);
     }
     c->opt.struct_size = sizeof(tw_options);
-    if ((c->opt.dedup != TW_DEDUP_EXACT && c->opt.dedup != TW_DEDUP_BLOOM) ||
+    if ((c->opt.dedup != TW_DEDUP_EXACT && c->opt.dedup != TW_DEDUP_BLOOM &&
+         c->opt.dedup != TW_DEDUP_BLOOM_CERTIFIED) ||
         (c->opt.reductions != TW_REDUCE_NONE && c->opt.reductions != TW_REDUCE_CLIQUE_PATHS)) {
         delete c;
         return TW_EINVAL;
@@ -1427,7 +1443,7 @@ tw_status tw_decide(tw_ctx *c, const tw_graph *gr, int32_t k, int32_t *out_yes, 
     Reduction red;
     if (c->opt.reductions)
         red = reduction_of(g, -1);
-    s = run_decide_reduced(c, g, c->opt.reductions ? &red : nullptr, k, kKeepPair, nullptr, levels, &yes, rs);
+    s = decide_checked(c, g, c->opt.reductions ? &red : nullptr, k, kKeepPair, levels, &yes, rs);
     free_levels(c, levels);
     if (s != TW_OK)
         return s;

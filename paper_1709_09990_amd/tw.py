@@ -16,7 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libtw.so")
 
 TW_OK, TW_EINVAL, TW_ENOMEM, TW_EDEVICE, TW_ECAPACITY = range(5)
-TW_DEDUP_EXACT, TW_DEDUP_BLOOM = 0, 1
+TW_DEDUP_EXACT, TW_DEDUP_BLOOM, TW_DEDUP_BLOOM_CERTIFIED = 0, 1, 2
 TW_K_ASCENDING, TW_K_LEARNED = 0, 1
 TW_REDUCE_NONE, TW_REDUCE_CLIQUE_PATHS = 0, 1
 

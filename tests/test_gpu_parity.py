@@ -403,3 +403,20 @@ def test_probe_rate_reference():
     for bad in ((64 << 20, 1 << 22, 3), (1024, 1 << 22, 0), (64 << 20, 0, 0)):
         with pytest.raises(T.TwError):
             T.probe_rate(*bad)
+
+
+def test_bloom_certified_answers_are_exact(oracle):
+    """Bloom search whose NO answers are re-decided exactly (§3.2 filter, exact
+    certificate): every answer equals the oracle's."""
+    from paper_1709_09990_amd import tw as T
+    graphs = [G.gnp(22, 0.3, 8100 + s) for s in range(4)] + [G.partial_ktree(36, 6, 0.3, 8200)]
+    with T.Context(device=0, dedup=T.TW_DEDUP_BLOOM_CERTIFIED) as c:
+        for rows in graphs:
+            tw = oracle.treewidth_bfs(rows, oracle.mmw(rows))
+            for k in (tw - 1, tw):
+                assert c.decide(rows, k)[0] == (k >= tw)
+            got, order, _ = c.solve(rows)
+            assert got == tw and oracle.order_width(rows, order) == tw
+        tws, _, status, _ = c.solve_batch(graphs)
+        assert list(status) == [0] * len(graphs)
+        assert list(tws) == [oracle.treewidth_bfs(r, oracle.mmw(r)) for r in graphs]
