@@ -100,6 +100,11 @@ typedef struct {
                                     allows, 2^16..2^22); a graph that outgrows its arena or table is
                                     re-solved alone by the tw_solve path */
     uint32_t batch_chunk;     /* states per work-queue task, multiple of 64 (0 = 256) */
+    int batch_schedule;       /* tw_solve_batch: TW_BATCH_ROUNDS (default) runs level rounds — per round one
+                                 launch expands the current level of every running graph (tasks sized
+                                 for about two per wave) and a second advances each graph; or
+                                 TW_BATCH_PERSISTENT, one persistent launch with a device work queue of
+                                 (graph, level) jobs cut into batch_chunk-state tasks */
     int reductions;           /* TW_REDUCE_NONE (default): the levels are those of Listing 1.
                                  TW_REDUCE_CLIQUE_PATHS: the first two optimisations of §3.1 — the
                                  vertices of a maximum clique C are never added to a state (some optimal
@@ -112,6 +117,7 @@ typedef struct {
 } tw_options;
 
 enum { TW_REDUCE_NONE = 0, TW_REDUCE_CLIQUE_PATHS = 1 };
+enum { TW_BATCH_ROUNDS = 0, TW_BATCH_PERSISTENT = 1 };
 
 /* Counters of one call (summed over every bound k and level it ran). */
 typedef struct {

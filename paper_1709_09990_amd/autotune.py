@@ -1,5 +1,6 @@
-"""Autotuner for the batched search: states per work-queue task, hash-table
-load factor and probe scheme, picked by timing candidates on a sample.
+"""Autotuner for the batched search: schedule (level rounds, or the persistent
+work queue with its states per task), hash-table load factor and probe
+scheme, picked by timing candidates on a sample.
 
     from paper_1709_09990_amd import autotune
     opts = autotune.tuned_options(graphs)          # cached per (n bucket, device)
@@ -20,7 +21,8 @@ import numpy as np
 
 from . import tw as T
 
-CHUNKS = (64, 128, 256, 512)
+# 0: level rounds (task size chosen per round); else the persistent queue with that many states per task
+CHUNKS = (0, 128, 256, 512)
 LOAD_FACTORS = (0.4, 0.5, 0.7)
 PROBES = (1, 2)
 
@@ -62,7 +64,8 @@ def tune(graphs, reps: int = 2, log=None) -> dict:
     results = []
     ref = None
     for chunk, lf, probe in itertools.product(CHUNKS, LOAD_FACTORS, PROBES):
-        opts = {"batch_chunk": chunk, "load_factor": lf, "probe": probe}
+        opts = {"batch_schedule": T.TW_BATCH_ROUNDS if chunk == 0 else T.TW_BATCH_PERSISTENT,
+                "batch_chunk": chunk, "load_factor": lf, "probe": probe}
         dt, tws = _time(graphs, opts, reps)
         if ref is None:
             ref = tws

@@ -62,7 +62,7 @@ struct BatchJob {
 };
 
 struct BatchQueue {
-    unsigned long long head;      // first job not yet exhausted
+    unsigned long long head;      // persistent queue: first job not yet exhausted; level rounds: the round's task size
     unsigned long long tail;      // jobs reserved
     unsigned long long capacity;
     uint32_t active;              // graphs still running
@@ -80,6 +80,10 @@ struct BatchArgs {
 };
 
 hipError_t launch_batch(const BatchArgs &a, unsigned grid_blocks, hipStream_t s);
+// One level round (a.jobs == nullptr): plan the tasks of every running graph's
+// current level into task_start[0..B], expand them, advance the graphs.
+hipError_t launch_batch_round(const BatchArgs &a, uint32_t B, uint32_t *task_start, unsigned grid_blocks,
+                              hipStream_t s);
 int batch_blocks_per_cu();
 
 }  // namespace twk

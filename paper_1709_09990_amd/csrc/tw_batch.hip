@@ -41,6 +41,8 @@ __device__ __forceinline__ T ld_relaxed(T *p)
 // Called by one lane: append a job for (g, level).
 __device__ void push_job(const BatchArgs &a, int g, int level, uint64_t begin, uint64_t count)
 {
+    if (!a.jobs)
+        return;  // level rounds: the graph's level fields are the next round's work
     const unsigned long long idx = atomicAdd(&a.q->tail, 1ull);
     if (idx >= a.q->capacity) {
         atomicOr(&a.q->abort, 1u);
@@ -100,7 +102,8 @@ __device__ void graph_done(const BatchArgs &a, BatchGraph *G, uint32_t status, i
 {
     if (lane == 0) {
         G->status = status;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (a.jobs)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         atomicSub(&a.q->active, 1u);
     }
 }
@@ -129,7 +132,8 @@ __device__ void start_bound(const BatchArgs &a, BatchGraph *G, int g, int k, int
 // (the search then moves down after a YES and up after a NO).
 __device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_count, int lane)
 {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (a.jobs)  // persistent queue: see the other waves' chunks of this level
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     BatchGraph *G = &a.graphs[g];
     const uint64_t cnt = read_lane64(ld_relaxed(&G->out_count), 0);
     const uint32_t ovf = first_lane32(ld_relaxed(&G->overflow));
@@ -192,6 +196,123 @@ __device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_c
     }
 }
 
+// States [lo, hi) of level `level` of graph g (the level starts at arena
+// offset `begin`): expand every state, insert feasible successors into the
+// graph's tagged table, append the new ones to its next level.  Whole wave.
+__device__ void process_chunk(const BatchArgs &a, int g, int level, uint64_t begin, uint64_t lo, uint64_t hi,
+                              int lane, uint64_t *stage_key, uint8_t *stage_v)
+{
+    BatchGraph *G = &a.graphs[g];
+    const int n = (int)first_lane32((uint32_t)G->n);
+    const int k = (int)first_lane32((uint32_t)G->k);
+    const uint64_t tag = (uint64_t)first_lane32(G->tag) << kBatchKeyBits;
+    const uint64_t tslots = read_lane64(G->table_slots, 0);
+    const uint64_t out_base = read_lane64(G->level_off[level + 1], 0);
+    const uint64_t arena_cap = read_lane64(G->arena_cap, 0);
+    const uint64_t max_fill = (uint64_t)((double)tslots * a.max_load);
+    uint64_t *keys = G->keys;
+    uint8_t *lastv = G->lastv;
+    uint64_t *table = G->table;
+    uint64_t Aj = lane < n ? G->adj[lane] : 0ull;
+    const uint8_t *paths = G->paths;
+    if (paths && lane < n) {
+        // edges of G_k+: pairs joined by more than k disjoint paths (§3.1)
+        const uint8_t *row = paths + lane * 64;
+        for (int u = 0; u < n; ++u)
+            if ((int)row[u] > k)
+                Aj |= 1ull << u;
+    }
+    const bool lane_allowed = ((G->allowed >> lane) & 1ull) != 0ull;
+    const uint64_t lanebit = 1ull << lane;
+
+    uint32_t staged = 0;
+    uint64_t feasible = 0;
+    bool overflow = false;
+    auto flush = [&]() {
+        if (staged == 0)
+            return;
+        wave_lds_sync();
+        uint64_t base = 0;
+        if (lane == 0)
+            base = atomicAdd(&G->out_count, (unsigned long long)staged);
+        base = read_lane64(base, 0);
+        if (base + staged > max_fill || out_base + base + staged > arena_cap) {
+            overflow = true;
+        } else {
+            for (uint32_t q = (uint32_t)lane; q < staged; q += 64) {
+                keys[out_base + base + q] = stage_key[q];
+                lastv[out_base + base + q] = stage_v[q];
+            }
+        }
+        wave_lds_sync();
+        staged = 0;
+    };
+
+    for (uint64_t chunk = lo; chunk < hi && !overflow; chunk += 64) {
+        const uint64_t idx = chunk + (uint64_t)lane;
+        const uint64_t mine = (idx < hi && level > 0) ? keys[begin + idx] : 0ull;
+        const int cnt = hi - chunk < 64 ? (int)(hi - chunk) : 64;
+        for (int s = 0; s < cnt; ++s) {
+            const uint64_t S = read_lane64(mine, s);
+            const bool feas = lane_feasible(S, Aj, lane, n, k) && lane_allowed;
+            const uint64_t fmask = ballot(feas);
+            feasible += (uint64_t)__popcll(fmask);
+            if (fmask == 0)
+                continue;
+            const uint64_t key = S | lanebit;
+            bool won = false;
+            if (feas) {
+                const uint64_t want = tag | key;
+                uint64_t slot = slot_in(key, tslots);
+                uint64_t cur = ld_relaxed(&table[slot]);
+                for (uint32_t p = 0;;) {
+                    if ((cur & ~kKeyMask) == tag) {
+                        if (cur == want)
+                            break;  // already claimed this level
+                        if (++p > a.max_probe) {
+                            overflow = true;
+                            break;
+                        }
+                        slot = slot + 1 == tslots ? 0 : slot + 1;
+                        cur = ld_relaxed(&table[slot]);
+                        continue;
+                    }
+                    // stale slot (older tag or never used): claim it
+                    const uint64_t prev = (uint64_t)atomicCAS((unsigned long long *)&table[slot],
+                                                              (unsigned long long)cur,
+                                                              (unsigned long long)want);
+                    if (prev == cur) {
+                        won = true;
+                        break;
+                    }
+                    cur = prev;
+                }
+            }
+            overflow = ballot(overflow) != 0ull;
+            const uint64_t winners = ballot(won);
+            const uint32_t nw = (uint32_t)__popcll(winners);
+            if (nw == 0)
+                continue;
+            if (staged + nw > (uint32_t)kBatchStage)
+                flush();
+            if (won) {
+                const uint32_t pos = staged + (uint32_t)lanes_below(winners);
+                stage_key[pos] = key;
+                stage_v[pos] = (uint8_t)lane;
+            }
+            staged += nw;
+        }
+    }
+    if (!overflow)
+        flush();
+    if (lane == 0) {
+        if (overflow)
+            atomicOr(&G->overflow, 1u);
+        if (feasible)
+            atomicAdd(&G->successors, (unsigned long long)feasible);
+    }
+}
+
 __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
 {
     __shared__ uint64_t stage_key[kBatchWaves][kBatchStage];
@@ -241,117 +362,9 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
         const int level = (int)first_lane32((uint32_t)J->level);
         const uint64_t begin = read_lane64(J->begin, 0);
         const uint64_t count = read_lane64(J->count, 0);
-        BatchGraph *G = &a.graphs[g];
-        const int n = (int)first_lane32((uint32_t)G->n);
-        const int k = (int)first_lane32((uint32_t)G->k);
-        const uint64_t tag = (uint64_t)first_lane32(G->tag) << kBatchKeyBits;
-        const uint64_t tslots = read_lane64(G->table_slots, 0);
-        const uint64_t out_base = read_lane64(G->level_off[level + 1], 0);
-        const uint64_t arena_cap = read_lane64(G->arena_cap, 0);
-        const uint64_t max_fill = (uint64_t)((double)tslots * a.max_load);
-        uint64_t *keys = G->keys;
-        uint8_t *lastv = G->lastv;
-        uint64_t *table = G->table;
-        uint64_t Aj = lane < n ? G->adj[lane] : 0ull;
-        const uint8_t *paths = G->paths;
-        if (paths && lane < n) {
-            // edges of G_k+: pairs joined by more than k disjoint paths (§3.1)
-            const uint8_t *row = paths + lane * 64;
-            for (int u = 0; u < n; ++u)
-                if ((int)row[u] > k)
-                    Aj |= 1ull << u;
-        }
-        const bool lane_allowed = ((G->allowed >> lane) & 1ull) != 0ull;
-        const uint64_t lanebit = 1ull << lane;
-
-        uint32_t staged = 0;
-        uint64_t feasible = 0;
-        bool overflow = false;
-        auto flush = [&]() {
-            if (staged == 0)
-                return;
-            wave_lds_sync();
-            uint64_t base = 0;
-            if (lane == 0)
-                base = atomicAdd(&G->out_count, (unsigned long long)staged);
-            base = read_lane64(base, 0);
-            if (base + staged > max_fill || out_base + base + staged > arena_cap) {
-                overflow = true;
-            } else {
-                for (uint32_t q = (uint32_t)lane; q < staged; q += 64) {
-                    keys[out_base + base + q] = stage_key[wv][q];
-                    lastv[out_base + base + q] = stage_v[wv][q];
-                }
-            }
-            wave_lds_sync();
-            staged = 0;
-        };
-
         const uint64_t lo = (uint64_t)c * a.chunk;
         const uint64_t hi = lo + a.chunk < count ? lo + a.chunk : count;
-        for (uint64_t chunk = lo; chunk < hi && !overflow; chunk += 64) {
-            const uint64_t idx = chunk + (uint64_t)lane;
-            const uint64_t mine = (idx < hi && level > 0) ? keys[begin + idx] : 0ull;
-            const int cnt = hi - chunk < 64 ? (int)(hi - chunk) : 64;
-            for (int s = 0; s < cnt; ++s) {
-                const uint64_t S = read_lane64(mine, s);
-                const bool feas = lane_feasible(S, Aj, lane, n, k) && lane_allowed;
-                const uint64_t fmask = ballot(feas);
-                feasible += (uint64_t)__popcll(fmask);
-                if (fmask == 0)
-                    continue;
-                const uint64_t key = S | lanebit;
-                bool won = false;
-                if (feas) {
-                    const uint64_t want = tag | key;
-                    uint64_t slot = slot_in(key, tslots);
-                    uint64_t cur = ld_relaxed(&table[slot]);
-                    for (uint32_t p = 0;;) {
-                        if ((cur & ~kKeyMask) == tag) {
-                            if (cur == want)
-                                break;  // already claimed this level
-                            if (++p > a.max_probe) {
-                                overflow = true;
-                                break;
-                            }
-                            slot = slot + 1 == tslots ? 0 : slot + 1;
-                            cur = ld_relaxed(&table[slot]);
-                            continue;
-                        }
-                        // stale slot (older tag or never used): claim it
-                        const uint64_t prev = (uint64_t)atomicCAS((unsigned long long *)&table[slot],
-                                                                  (unsigned long long)cur,
-                                                                  (unsigned long long)want);
-                        if (prev == cur) {
-                            won = true;
-                            break;
-                        }
-                        cur = prev;
-                    }
-                }
-                overflow = ballot(overflow) != 0ull;
-                const uint64_t winners = ballot(won);
-                const uint32_t nw = (uint32_t)__popcll(winners);
-                if (nw == 0)
-                    continue;
-                if (staged + nw > (uint32_t)kBatchStage)
-                    flush();
-                if (won) {
-                    const uint32_t pos = staged + (uint32_t)lanes_below(winners);
-                    stage_key[wv][pos] = key;
-                    stage_v[wv][pos] = (uint8_t)lane;
-                }
-                staged += nw;
-            }
-        }
-        if (!overflow)
-            flush();
-        if (lane == 0) {
-            if (overflow)
-                atomicOr(&G->overflow, 1u);
-            if (feasible)
-                atomicAdd(&G->successors, (unsigned long long)feasible);
-        }
+        process_chunk(a, g, level, begin, lo, hi, lane, stage_key[wv], stage_v[wv]);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         uint32_t d = 0;
         if (lane == 0)
@@ -362,7 +375,124 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Level rounds.  One launch expands the current level of every running graph,
+// its chunks laid out by a prefix sum over the graphs; a second launch
+// advances every graph that ran a level (next level, next bound, or done).
+// The kernel boundaries order the levels, so no wave waits on another and no
+// cache maintenance runs inside a launch (on this multi-XCD part every
+// agent-scope acquire invalidates an XCD's L2 and every release writes it
+// back, which the persistent queue pays per task).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t level_count(const BatchArgs &a, uint32_t g)
+{
+    const BatchGraph *G = &a.graphs[g];
+    if (G->status != kBatchRunning)
+        return 0;
+    return G->level_off[G->level + 1] - G->level_off[G->level];
+}
+
+// One workgroup: this round's states per task (about two tasks per wave,
+// 64..1024, a multiple of 64) and the first task of every graph.
+__global__ __launch_bounds__(1024) void plan_kernel(BatchArgs a, uint32_t B, uint32_t *task_start, uint32_t nwaves)
+{
+    __shared__ unsigned long long part[1024];
+    __shared__ uint32_t scan[1024];
+    const uint32_t t = threadIdx.x;
+    unsigned long long sum = 0;
+    for (uint32_t g = t; g < B; g += 1024)
+        sum += level_count(a, g);
+    part[t] = sum;
+    __syncthreads();
+    for (uint32_t off = 512; off; off >>= 1) {
+        if (t < off)
+            part[t] += part[t + off];
+        __syncthreads();
+    }
+    const unsigned long long total = part[0];
+    uint64_t c = (total + 2ull * nwaves - 1) / (2ull * nwaves);
+    c = (c + 63) / 64 * 64;
+    c = c < 64 ? 64 : (c > 1024 ? 1024 : c);
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < B; base += 1024) {
+        const uint32_t g = base + t;
+        const uint32_t cnt = g < B ? (uint32_t)((level_count(a, g) + c - 1) / c) : 0u;
+        scan[t] = cnt;
+        __syncthreads();
+        for (uint32_t off = 1; off < 1024; off <<= 1) {
+            const uint32_t v = t >= off ? scan[t - off] : 0u;
+            __syncthreads();
+            scan[t] += v;
+            __syncthreads();
+        }
+        if (g < B)
+            task_start[g] = carry + scan[t] - cnt;
+        carry += scan[1023];
+        __syncthreads();
+    }
+    if (t == 0) {
+        task_start[B] = carry;
+        a.q->head = c;  // the queue's head word carries the round's task size
+    }
+}
+
+__global__ __launch_bounds__(kBatchBlock) void round_kernel(BatchArgs a, uint32_t B, const uint32_t *task_start)
+{
+    __shared__ uint64_t stage_key[kBatchWaves][kBatchStage];
+    __shared__ uint8_t stage_v[kBatchWaves][kBatchStage];
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = (int)(threadIdx.x >> 6);
+    const uint32_t total = task_start[B];
+    const uint64_t c = a.q->head;
+    const uint32_t nw = gridDim.x * kBatchWaves;
+    for (uint32_t t = blockIdx.x * kBatchWaves + wv; t < total; t += nw) {
+        // graph of task t: the last g with task_start[g] <= t
+        uint32_t lo = 0, hi = B;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (task_start[mid] <= t)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const BatchGraph *G = &a.graphs[lo];
+        const int level = (int)first_lane32((uint32_t)G->level);
+        const uint64_t begin = read_lane64(G->level_off[level], 0);
+        const uint64_t count = read_lane64(G->level_off[level + 1], 0) - begin;
+        const uint64_t first = (uint64_t)(t - task_start[lo]) * c;
+        const uint64_t last = first + c < count ? first + c : count;
+        process_chunk(a, (int)lo, level, begin, first, last, lane, stage_key[wv], stage_v[wv]);
+    }
+}
+
+// One wave per graph: close the level it ran this round.
+__global__ __launch_bounds__(kBatchBlock) void advance_kernel(BatchArgs a, uint32_t B)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const uint32_t g = blockIdx.x * kBatchWaves + (threadIdx.x >> 6);
+    if (g >= B)
+        return;
+    const BatchGraph *G = &a.graphs[g];
+    if (first_lane32(G->status) != kBatchRunning)
+        return;
+    const int level = (int)first_lane32((uint32_t)G->level);
+    const uint64_t count = read_lane64(G->level_off[level + 1], 0) - read_lane64(G->level_off[level], 0);
+    finish_level(a, (int)g, level, count, lane);
+}
+
 }  // namespace
+
+hipError_t launch_batch_round(const BatchArgs &a, uint32_t B, uint32_t *task_start, unsigned grid_blocks,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, a, B, task_start,
+                       (uint32_t)(grid_blocks * kBatchWaves));
+    hipLaunchKernelGGL(round_kernel, dim3(grid_blocks), dim3(kBatchBlock), 0, s, a, B,
+                       (const uint32_t *)task_start);
+    hipLaunchKernelGGL(advance_kernel, dim3((B + kBatchWaves - 1) / kBatchWaves), dim3(kBatchBlock), 0, s, a, B);
+    return hipGetLastError();
+}
 
 int batch_blocks_per_cu()
 {

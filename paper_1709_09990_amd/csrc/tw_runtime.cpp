@@ -1151,7 +1151,40 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
     const unsigned grid = (unsigned)(c->cu_count * twk::batch_blocks_per_cu());
     if (c->opt.timing)
         HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-    HIP_TRY(c, twk::launch_batch(a, grid, c->stream));
+    if (c->opt.batch_schedule == TW_BATCH_PERSISTENT) {
+        HIP_TRY(c, twk::launch_batch(a, grid, c->stream));
+    } else {
+        // level rounds until no graph runs; the host looks every 8 rounds
+        a.jobs = nullptr;
+        Buf d_tasks;
+        tw_status ts = acquire(c, d_tasks, (B + 1) * sizeof(uint32_t));
+        if (ts != TW_OK) {
+            cleanup();
+            return ts;
+        }
+        // every graph's search ends within n bounds of n levels each
+        const int max_rounds = 64 * 64 + 64;
+        bool finished = false;
+        for (int round = 0; round < max_rounds && !finished; ++round) {
+            hipError_t e = twk::launch_batch_round(a, (uint32_t)B, (uint32_t *)d_tasks.p, grid, c->stream);
+            if (e == hipSuccess && (round & 7) == 7)
+                e = hipMemcpyAsync(&hq, d_q.p, sizeof hq, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess && (round & 7) == 7)
+                e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) {
+                release(c, d_tasks);
+                cleanup();
+                return fail(c, TW_EDEVICE, "batch round %d: %s", round, hipGetErrorString(e));
+            }
+            if ((round & 7) == 7)
+                finished = hq.active == 0 || hq.abort;
+        }
+        release(c, d_tasks);
+        if (!finished) {
+            cleanup();
+            return fail(c, TW_EDEVICE, "batch rounds did not finish within %d rounds", max_rounds);
+        }
+    }
     if (c->opt.timing)
         HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
     HIP_TRY(c, hipMemcpyAsync(hg.data(), d_graphs.p, B * sizeof(twk::BatchGraph), hipMemcpyDeviceToHost,
@@ -1341,7 +1374,8 @@ tw_status tw_ctx_create(const tw_options *options, tw_ctx **out)
     c->opt.struct_size = sizeof(tw_options);
     if ((c->opt.dedup != TW_DEDUP_EXACT && c->opt.dedup != TW_DEDUP_BLOOM &&
          c->opt.dedup != TW_DEDUP_BLOOM_CERTIFIED) ||
-        (c->opt.reductions != TW_REDUCE_NONE && c->opt.reductions != TW_REDUCE_CLIQUE_PATHS)) {
+        (c->opt.reductions != TW_REDUCE_NONE && c->opt.reductions != TW_REDUCE_CLIQUE_PATHS) ||
+        (c->opt.batch_schedule != TW_BATCH_ROUNDS && c->opt.batch_schedule != TW_BATCH_PERSISTENT)) {
         delete c;
         return TW_EINVAL;
     }

@@ -19,6 +19,7 @@ TW_OK, TW_EINVAL, TW_ENOMEM, TW_EDEVICE, TW_ECAPACITY = range(5)
 TW_DEDUP_EXACT, TW_DEDUP_BLOOM, TW_DEDUP_BLOOM_CERTIFIED = 0, 1, 2
 TW_K_ASCENDING, TW_K_LEARNED = 0, 1
 TW_REDUCE_NONE, TW_REDUCE_CLIQUE_PATHS = 0, 1
+TW_BATCH_ROUNDS, TW_BATCH_PERSISTENT = 0, 1
 
 
 class TwError(RuntimeError):
@@ -47,6 +48,7 @@ class _Options(ctypes.Structure):
         ("partition", ctypes.c_int),
         ("batch_graph_states", ctypes.c_uint64),
         ("batch_chunk", ctypes.c_uint32),
+        ("batch_schedule", ctypes.c_int),
         ("reductions", ctypes.c_int),
     ]
 
@@ -249,7 +251,7 @@ class Context:
                  load_factor: float = 0.0, max_states: int = 0, capacity_override: int = 0,
                  timing: bool = False, k_policy: int = TW_K_ASCENDING, weights_path: str | None = None,
                  batch_graph_states: int = 0, batch_chunk: int = 0, probe: int = 0, partition: int = 0,
-                 reductions: int = TW_REDUCE_NONE):
+                 reductions: int = TW_REDUCE_NONE, batch_schedule: int = TW_BATCH_ROUNDS):
         L = load()
         self._L = L
         o = _Options()
@@ -269,6 +271,7 @@ class Context:
         o.batch_graph_states = batch_graph_states
         o.batch_chunk = batch_chunk
         o.reductions = reductions
+        o.batch_schedule = batch_schedule
         h = ctypes.c_void_p()
         st = L.tw_ctx_create(ctypes.byref(o), ctypes.byref(h))
         if st != TW_OK:
