@@ -358,13 +358,13 @@ def test_batch_graph_stats_peak(oracle):
 
 
 def test_autotune_candidates_agree(tmp_path, monkeypatch):
-    """Every autotuner candidate (tile size, load factor, probe scheme) gives
-    the same answers; the tuned choice is cached and reused."""
+    """Every autotuner candidate (schedule and tile size, load factor, probe
+    scheme) gives the same answers; the tuned choice is cached and reused."""
     from paper_1709_09990_amd import autotune
     monkeypatch.setenv("TW_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     graphs = G.workload_batch(24, seed0=36000, n_lo=10, n_hi=22)
     opts = autotune.tuned_options(graphs, sample=24)
-    assert set(opts) == {"batch_chunk", "load_factor", "probe"}
+    assert set(opts) == {"batch_schedule", "batch_chunk", "load_factor", "probe"}
     assert autotune.tuned_options(graphs) == opts
 
 

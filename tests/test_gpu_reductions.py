@@ -104,7 +104,7 @@ def test_reduced_solve_equals_plain(oracle):
 
 def test_reduced_batch_equals_single(oracle):
     from paper_1709_09990_amd import tw as T
-    graphs = G.workload_batch(64, seed0=7600, n_lo=10, n_hi=30)
+    graphs = G.workload_batch(40, seed0=7600, n_lo=10, n_hi=26)
     want = [oracle.treewidth_bfs(r, oracle.mmw(r)) for r in graphs]
     with T.Context(device=0, reductions=T.TW_REDUCE_CLIQUE_PATHS) as r:
         tws, orders, status, st = r.solve_batch(graphs)
@@ -140,7 +140,7 @@ def test_learned_start_with_reductions_is_exact(oracle):
     import os
     from paper_1709_09990_amd import tw as T
     w = os.path.join(os.path.dirname(T.__file__), "weights", "mpnn_mixture_n16_30_reduced.bin")
-    graphs = G.workload_batch(48, seed0=7700, n_lo=16, n_hi=30)
+    graphs = G.workload_batch(32, seed0=7700, n_lo=14, n_hi=26)
     want = [oracle.treewidth_bfs(r, oracle.mmw(r)) for r in graphs]
     with T.Context(device=0, reductions=T.TW_REDUCE_CLIQUE_PATHS, k_policy=T.TW_K_LEARNED, weights_path=w) as c:
         tws, orders, status, _ = c.solve_batch(graphs)
