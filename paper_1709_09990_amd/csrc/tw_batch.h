@@ -24,6 +24,7 @@ struct BatchGraph {
     uint64_t adj[64];
     uint64_t *keys;          // arena: the levels of the current bound, back to back
     uint8_t *lastv;
+    uint32_t *parent;        // per state: index of the state it came from, within the level below
     uint64_t arena_cap;      // states the arena holds
     uint64_t *table;         // tagged open-addressing table (tag << 48 | key), zero-initialised
     uint64_t table_slots;

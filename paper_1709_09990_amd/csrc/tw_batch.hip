@@ -23,7 +23,7 @@ namespace {
 
 constexpr int kBatchBlock = 256;
 constexpr int kBatchWaves = kBatchBlock / 64;
-constexpr int kBatchStage = 512;
+constexpr int kBatchStage = 384;  // 13 bytes per staged winner: 8 blocks of 4 waves fit a CU
 constexpr uint64_t kKeyMask = (1ull << kBatchKeyBits) - 1;
 
 template <typename T>
@@ -60,9 +60,10 @@ __device__ void push_job(const BatchArgs &a, int g, int level, uint64_t begin, u
 }
 
 // Whole wave, after a YES at bound G->k with G->L levels in the arena: follow
-// the vertex that created each state back to the empty set (§3.1 stores one
-// creator per state; the predecessor is found by a wave-wide scan of the
-// level below), then the k+1 vertices never eliminated, ascending.
+// the vertex that created each state and the index of the state it came from
+// (both stored per state) back to the empty set, then the k+1 vertices never
+// eliminated, ascending.  Each step is checked: the predecessor must be the
+// state minus that vertex (else the host's width check rejects the order).
 __device__ void capture_order(BatchGraph *G, int lane)
 {
     const int L = G->L;
@@ -70,25 +71,16 @@ __device__ void capture_order(BatchGraph *G, int lane)
     uint64_t S = SL;
     uint64_t idx = 0;
     for (int i = L; i >= 1; --i) {
-        const int v = (int)first_lane32(G->lastv[G->level_off[i] + idx]);
+        const uint64_t at = G->level_off[i] + idx;
+        const int v = (int)first_lane32(G->lastv[at]);
         if (lane == 0)
             G->order[i - 1] = v;
         S &= ~(1ull << v);
         if (i == 1)
             break;
-        const uint64_t b = G->level_off[i - 1];
-        const uint64_t cnt = G->level_off[i] - b;
-        idx = ~0ull;
-        for (uint64_t t0 = 0; t0 < cnt; t0 += 64) {
-            const uint64_t t = t0 + (uint64_t)lane;
-            const uint64_t hit = ballot(t < cnt && G->keys[b + t] == S);
-            if (hit) {
-                idx = t0 + (uint64_t)__builtin_ctzll(hit);
-                break;
-            }
-        }
-        if (idx == ~0ull)
-            break;  // inconsistent arena: the host's width check rejects the order
+        idx = (uint64_t)first_lane32(G->parent[at]);
+        if (read_lane64(G->keys[G->level_off[i - 1] + idx], 0) != S)
+            break;
     }
     if (lane == 0) {
         int t = L;
@@ -200,7 +192,7 @@ __device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_c
 // offset `begin`): expand every state, insert feasible successors into the
 // graph's tagged table, append the new ones to its next level.  Whole wave.
 __device__ void process_chunk(const BatchArgs &a, int g, int level, uint64_t begin, uint64_t lo, uint64_t hi,
-                              int lane, uint64_t *stage_key, uint8_t *stage_v)
+                              int lane, uint64_t *stage_key, uint8_t *stage_v, uint32_t *stage_p)
 {
     BatchGraph *G = &a.graphs[g];
     const int n = (int)first_lane32((uint32_t)G->n);
@@ -212,6 +204,7 @@ __device__ void process_chunk(const BatchArgs &a, int g, int level, uint64_t beg
     const uint64_t max_fill = (uint64_t)((double)tslots * a.max_load);
     uint64_t *keys = G->keys;
     uint8_t *lastv = G->lastv;
+    uint32_t *parent = G->parent;
     uint64_t *table = G->table;
     uint64_t Aj = lane < n ? G->adj[lane] : 0ull;
     const uint8_t *paths = G->paths;
@@ -242,6 +235,7 @@ __device__ void process_chunk(const BatchArgs &a, int g, int level, uint64_t beg
             for (uint32_t q = (uint32_t)lane; q < staged; q += 64) {
                 keys[out_base + base + q] = stage_key[q];
                 lastv[out_base + base + q] = stage_v[q];
+                parent[out_base + base + q] = stage_p[q];
             }
         }
         wave_lds_sync();
@@ -299,6 +293,7 @@ __device__ void process_chunk(const BatchArgs &a, int g, int level, uint64_t beg
                 const uint32_t pos = staged + (uint32_t)lanes_below(winners);
                 stage_key[pos] = key;
                 stage_v[pos] = (uint8_t)lane;
+                stage_p[pos] = (uint32_t)(chunk + (uint64_t)s);
             }
             staged += nw;
         }
@@ -316,6 +311,7 @@ __device__ void process_chunk(const BatchArgs &a, int g, int level, uint64_t beg
 __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
 {
     __shared__ uint64_t stage_key[kBatchWaves][kBatchStage];
+    __shared__ uint32_t stage_p[kBatchWaves][kBatchStage];
     __shared__ uint8_t stage_v[kBatchWaves][kBatchStage];
     const int lane = (int)(threadIdx.x & 63);
     const int wv = (int)(threadIdx.x >> 6);
@@ -364,7 +360,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
         const uint64_t count = read_lane64(J->count, 0);
         const uint64_t lo = (uint64_t)c * a.chunk;
         const uint64_t hi = lo + a.chunk < count ? lo + a.chunk : count;
-        process_chunk(a, g, level, begin, lo, hi, lane, stage_key[wv], stage_v[wv]);
+        process_chunk(a, g, level, begin, lo, hi, lane, stage_key[wv], stage_v[wv], stage_p[wv]);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         uint32_t d = 0;
         if (lane == 0)
@@ -440,6 +436,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(BatchArgs a, uint32_t B, uin
 __global__ __launch_bounds__(kBatchBlock) void round_kernel(BatchArgs a, uint32_t B, const uint32_t *task_start)
 {
     __shared__ uint64_t stage_key[kBatchWaves][kBatchStage];
+    __shared__ uint32_t stage_p[kBatchWaves][kBatchStage];
     __shared__ uint8_t stage_v[kBatchWaves][kBatchStage];
     const int lane = (int)(threadIdx.x & 63);
     const int wv = (int)(threadIdx.x >> 6);
@@ -462,7 +459,7 @@ __global__ __launch_bounds__(kBatchBlock) void round_kernel(BatchArgs a, uint32_
         const uint64_t count = read_lane64(G->level_off[level + 1], 0) - begin;
         const uint64_t first = (uint64_t)(t - task_start[lo]) * c;
         const uint64_t last = first + c < count ? first + c : count;
-        process_chunk(a, (int)lo, level, begin, first, last, lane, stage_key[wv], stage_v[wv]);
+        process_chunk(a, (int)lo, level, begin, first, last, lane, stage_key[wv], stage_v[wv], stage_p[wv]);
     }
 }
 

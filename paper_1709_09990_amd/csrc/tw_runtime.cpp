@@ -1052,9 +1052,10 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
         slot_total += slots[b];
     }
     const size_t job_bytes = (job_cap * sizeof(twk::BatchJob) + 15) / 16 * 16;
-    Buf d_graphs, d_jobs, d_q, d_keys, d_lastv, d_table, d_paths;
+    Buf d_graphs, d_jobs, d_q, d_keys, d_lastv, d_parent, d_table, d_paths;
     auto cleanup = [&]() {
         release(c, d_paths);
+        release(c, d_parent);
         release(c, d_graphs);
         release(c, d_jobs);
         release(c, d_q);
@@ -1071,6 +1072,8 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
         s = acquire(c, d_keys, arena_total * sizeof(uint64_t));
     if (s == TW_OK)
         s = acquire(c, d_lastv, arena_total);
+    if (s == TW_OK)
+        s = acquire(c, d_parent, arena_total * sizeof(uint32_t));
     if (s == TW_OK)
         s = acquire(c, d_table, slot_total * sizeof(uint64_t));
     if (s == TW_OK && reds)
@@ -1091,6 +1094,7 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
             G.adj[j] = g.rows[j];
         G.keys = (uint64_t *)d_keys.p + aoff[b];
         G.lastv = (uint8_t *)d_lastv.p + aoff[b];
+        G.parent = (uint32_t *)d_parent.p + aoff[b];
         G.arena_cap = arenas[b];
         G.table = (uint64_t *)d_table.p + soff[b];
         G.table_slots = slots[b];
@@ -1254,7 +1258,7 @@ tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vect
     for (size_t q = 0; q <= ids.size(); ++q) {
         uint64_t need = 0;
         if (q < ids.size())
-            need = arena_of[(size_t)ids[q]] * 9 + arena_of[(size_t)ids[q]] * 8 + 4096;
+            need = arena_of[(size_t)ids[q]] * 13 + arena_of[(size_t)ids[q]] * 8 + 4096;
         if (q == ids.size() || (!group.empty() && used + need > budget)) {
             tw_status s = batch_launch(c, graphs, reds, lbs, k0s, arenas, group, out_tw, out_orders, offs,
                                        out_status, single_ids, outcomes, rs);
@@ -1571,13 +1575,13 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
     std::vector<int> batch_ids;   // graphs that go into the persistent launch
     std::vector<int> single_ids;  // graphs solved one at a time
     // default arena: as large as half of free device memory allows over the
-    // batch (17 bytes per state: key, creator byte, table slot), 2^16..2^22
+    // batch (21 bytes per state: key, creator byte, parent index, table slot), 2^16..2^22
     uint64_t default_arena = c->opt.batch_graph_states;
     if (!default_arena) {
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
             free_b = (size_t)16 << 30;
-        const uint64_t per = (uint64_t)(free_b / 2) / std::max<uint64_t>(1, count) / 17;
+        const uint64_t per = (uint64_t)(free_b / 2) / std::max<uint64_t>(1, count) / 21;
         default_arena = 1ull << 16;
         while (default_arena < (1ull << 22) && default_arena * 2 <= per)
             default_arena *= 2;

@@ -420,3 +420,11 @@ def test_bloom_certified_answers_are_exact(oracle):
         tws, _, status, _ = c.solve_batch(graphs)
         assert list(status) == [0] * len(graphs)
         assert list(tws) == [oracle.treewidth_bfs(r, oracle.mmw(r)) for r in graphs]
+
+
+def test_invalid_options_rejected():
+    from paper_1709_09990_amd import tw as T
+    for kw in ({"dedup": 5}, {"reductions": 3}, {"batch_schedule": 2}):
+        with pytest.raises(T.TwError) as e:
+            T.Context(device=0, **kw)
+        assert e.value.status == T.TW_EINVAL
