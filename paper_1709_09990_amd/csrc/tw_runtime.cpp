@@ -1306,6 +1306,8 @@ bool read_weights(const char *path, std::vector<float> &params)
 //    (never below the default); a graph whose arena would exceed kArenaMax is
 //    sent to the single-graph path at once instead of overflowing in the batch.
 constexpr uint64_t kArenaMax = 1ull << 23;
+// arena of the second batched attempt for graphs that outgrew the first
+constexpr uint64_t kArenaRetry = 1ull << 24;
 
 tw_status predict_starts(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<int> &lbs,
                          const std::vector<int> &ids, std::vector<int> &k0s, std::vector<uint64_t> &arena_of,
@@ -1655,10 +1657,31 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
         batch_ids.swap(keep);
     }
     const std::vector<Reduction> *rp = c->opt.reductions ? &reds : nullptr;
+    const size_t before = single_ids.size();
     st = batch_run(c, graphs, rp, lbs, k0s, arena_of, batch_ids, out_tw, out_orders, offs, out_status,
                    single_ids, outcomes, rs);
     if (st != TW_OK)
         return st;
+    // graphs whose levels outgrew their arena: once more together, with 4x the
+    // arena (up to kArenaRetry states), before the one-at-a-time path (level
+    // rounds only: the persistent queue measured slower with the retry)
+    if (!c->opt.batch_graph_states && c->opt.batch_schedule == TW_BATCH_ROUNDS && single_ids.size() > before) {
+        std::vector<int> retry(single_ids.begin() + (long)before, single_ids.end());
+        single_ids.resize(before);
+        std::vector<int> again;
+        for (int t : retry) {
+            if (arena_of[(size_t)t] < kArenaRetry) {
+                arena_of[(size_t)t] = std::min<uint64_t>(arena_of[(size_t)t] * 4, kArenaRetry);
+                again.push_back(t);
+            } else {
+                single_ids.push_back(t);
+            }
+        }
+        st = batch_run(c, graphs, rp, lbs, k0s, arena_of, again, out_tw, out_orders, offs, out_status,
+                       single_ids, outcomes, rs);
+        if (st != TW_OK)
+            return st;
+    }
     for (int t : single_ids) {
         GraphOutcome oc;
         tw_status s = solve_one(c, graphs[(size_t)t], rp ? &reds[(size_t)t] : nullptr, lbs[(size_t)t],
