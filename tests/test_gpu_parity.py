@@ -428,3 +428,18 @@ def test_invalid_options_rejected():
         with pytest.raises(T.TwError) as e:
             T.Context(device=0, **kw)
         assert e.value.status == T.TW_EINVAL
+
+
+def test_batch_rounds_many_graphs(oracle):
+    """More graphs than one plan tile (1024): the level-round schedule and the
+    persistent queue both give the oracle's treewidths."""
+    from paper_1709_09990_amd import tw as T
+    graphs = G.workload_batch(1100, seed0=39000, n_lo=6, n_hi=13)
+    want = [oracle.treewidth_bfs(r, oracle.mmw(r)) for r in graphs]
+    for sched in (T.TW_BATCH_ROUNDS, T.TW_BATCH_PERSISTENT):
+        with T.Context(device=0, batch_schedule=sched) as c:
+            tws, orders, status, _ = c.solve_batch(graphs)
+        assert list(status) == [0] * len(graphs)
+        assert list(tws) == want, sched
+        for rows, tw, order in list(zip(graphs, tws, orders))[::50]:
+            assert oracle.order_width(rows, order) == tw
