@@ -94,7 +94,7 @@ typedef struct {
                                  partition by partition into table slices of <= 64 MB (n <= 58).  The
                                  two-phase form keeps the probes in the Infinity Cache but pays a
                                  second pass; it measured slower on MI355X for the levels tried */
-    /* tw_solve_batch: graphs with n <= 48 run in one persistent launch, each with
+    /* tw_solve_batch: graphs with n <= 48 run together on the device, each with
        its own state arena (all levels of its current bound) and hash table. */
     uint64_t batch_graph_states; /* arena states per graph (0 = as many as half the free device memory
                                     allows, 2^16..2^22); a graph that outgrows its arena or table is
@@ -149,16 +149,21 @@ tw_status tw_decide(tw_ctx *ctx, const tw_graph *g, int32_t k, int32_t *out_yes,
  * after a YES, up after a NO) with options.k_policy = TW_K_LEARNED.  out_order[t] is the t-th vertex eliminated;
  * it must hold n entries.  The order is rebuilt from the last level by
  * following, for each state, the vertex that created it back to the empty
- * set, then the k+1 remaining vertices in ascending index; its width is
- * checked to equal *out_tw before returning. */
+ * set (from the kept levels, or, when they were too large to keep, from a
+ * search restricted to the subsets of one last-level state), then the k+1
+ * remaining vertices in ascending index; its width is checked to equal
+ * *out_tw before returning. */
 tw_status tw_solve(tw_ctx *ctx, const tw_graph *g, int32_t *out_tw, int32_t *out_order, tw_stats *stats);
 
 /* tw_solve for count graphs of uneven size.  out_tw[count], out_status[count];
  * out_orders holds the orders back to back (sum of n entries, graph order).
- * Graphs with n <= 48 are solved together in one persistent kernel: a device
- * work queue of (graph, level) jobs cut into chunks, the last chunk of a level
- * advancing that graph's level or bound on the device; the others (and any
- * graph whose arena or table fills up) go through the tw_solve path.  The
+ * Graphs with n <= 48 are solved together on the device, each with its own
+ * arena (every level of its current bound) and tagged hash table, by level
+ * rounds (default: one launch expands the current level of every running
+ * graph, a second advances each graph's level or bound) or by one persistent
+ * kernel with a device work queue (options.batch_schedule).  Graphs whose
+ * levels outgrow their arena get one more batched attempt with four times the
+ * arena (level rounds), and then, like the others, the tw_solve path.  The
  * treewidths equal tw_solve's; each order is checked by fill-in to have
  * exactly that width (several orders may qualify).
  * With options.k_policy = TW_K_LEARNED each graph starts at the bound the
@@ -174,7 +179,7 @@ typedef struct {
     uint64_t states_expanded; /* states expanded over this graph's whole search */
     int32_t start_k;          /* first bound tried (lower bound, or the learned prediction) */
     uint32_t decisions;       /* bounds tried */
-    int32_t path;             /* 0: persistent batch kernel, 1: single-graph path, 2: trivial (tw = n-1) */
+    int32_t path;             /* 0: batched on the device, 1: single-graph path, 2: trivial (tw = n-1) */
     int32_t reserved;
 } tw_graph_stats;
 

@@ -1,4 +1,5 @@
-// Device structures of the batched persistent search (many graphs, one launch).
+// Device structures of the batched search (many graphs solved together: level
+// rounds, or one persistent launch with a work queue).
 #pragma once
 
 #include <hip/hip_runtime.h>

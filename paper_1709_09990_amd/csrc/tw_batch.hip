@@ -1,20 +1,21 @@
-// Batched persistent search: every graph of a batch runs its own ascending-k
-// level loop (§3.1, Listing 1) inside ONE launch.
+// Batched search: every graph of a batch runs its own level loop (§3.1,
+// Listing 1), from the bound the host gives it (lower bound or prediction),
+// moving until a YES at t meets a NO at t-1 (or t = lower bound); the order of
+// each YES is captured before the arena is reused.  Each graph has its own
+// arena (all levels of its current bound, back to back, with each state's
+// creating vertex and parent index for the order) and its own hash table.
+// Table slots carry a 16-bit tag above the 48-bit state; a slot whose tag is
+// not the level's tag counts as empty, so tables are never cleared.
 //
-// Work is a device queue of jobs, one job per (graph, level); a job is cut
-// into chunks of `chunk` states and every wave of the persistent grid takes
-// chunks from the job at the queue head.  The wave that finishes the last
-// chunk of a level advances that graph alone: next level, next bound k after a
-// NO (empty level), or done after a YES — so graphs of different sizes never
-// wait for each other.  Each graph has its own arena (all levels of its
-// current bound, back to back, for the order backtrack) and its own hash
-// table.  A graph's search starts at the bound the host gives it (lower bound
-// or prediction) and moves until a YES at t meets a NO at t-1 (or t = lower
-// bound); the order of each YES is captured before the arena is reused.  Table slots carry a 16-bit tag above the 48-bit state; a slot whose
-// tag is not the level's tag counts as empty, so tables are never cleared.
-//
-// Exit: every wave leaves once no graph is running, or after spin_limit
-// consecutive sleeps without work (abort flag; the host reports an error).
+// Two schedules share the per-chunk expansion (process_chunk) and the
+// per-graph advance (finish_level):
+//  * level rounds (round_kernel and friends, at the end of this file): one
+//    launch per level of every running graph, then one that advances them;
+//  * one persistent launch (batch_kernel): a device queue of jobs, one per
+//    (graph, level), cut into chunks that every wave of the grid takes; the
+//    wave finishing a level's last chunk advances that graph alone.  Exit:
+//    every wave leaves once no graph is running, or after spin_limit
+//    consecutive sleeps without work (abort flag; the host reports an error).
 #include "tw_batch.h"
 #include "tw_wave.h"
 

@@ -1022,7 +1022,7 @@ tw_status solve_one(tw_ctx *c, const Graph &g, const Reduction *red, int lb, int
     return TW_OK;
 }
 
-// One persistent launch over the graphs ids[0..B): start bound k0s[t] and
+// One batched solve (level rounds or one persistent launch) over the graphs ids[0..B): start bound k0s[t] and
 // arena of arena[t] states for graph ids[t].  Graphs that finish get their
 // tw, order and outcome; graphs whose arena or table filled up are appended
 // to single_ids for the tw_solve path.
@@ -1574,7 +1574,7 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
     std::vector<int> lbs(count, 0), k0s(count, 0);
     std::vector<uint64_t> arena_of(count, 0);
     std::vector<GraphOutcome> outcomes(count);
-    std::vector<int> batch_ids;   // graphs that go into the persistent launch
+    std::vector<int> batch_ids;   // graphs solved together on the device
     std::vector<int> single_ids;  // graphs solved one at a time
     // default arena: as large as half of free device memory allows over the
     // batch (21 bytes per state: key, creator byte, parent index, table slot), 2^16..2^22
