@@ -409,7 +409,7 @@ def test_bloom_certified_answers_are_exact(oracle):
     """Bloom search whose NO answers are re-decided exactly (§3.2 filter, exact
     certificate): every answer equals the oracle's."""
     from paper_1709_09990_amd import tw as T
-    graphs = [G.gnp(22, 0.3, 8100 + s) for s in range(4)] + [G.partial_ktree(36, 6, 0.3, 8200)]
+    graphs = [G.gnp(20, 0.3, 8100 + s) for s in range(4)] + [G.partial_ktree(34, 5, 0.3, 8200)]
     with T.Context(device=0, dedup=T.TW_DEDUP_BLOOM_CERTIFIED) as c:
         for rows in graphs:
             tw = oracle.treewidth_bfs(rows, oracle.mmw(rows))
