@@ -443,3 +443,20 @@ def test_batch_rounds_many_graphs(oracle):
         assert list(tws) == want, sched
         for rows, tw, order in list(zip(graphs, tws, orders))[::50]:
             assert oracle.order_width(rows, order) == tw
+
+
+def test_batch_mixed_sizes_up_to_64(oracle):
+    """Graphs above the batched limit (n > 48) go through the single-graph path
+    inside the same call; trivial graphs (tw = n - 1) need no search."""
+    from paper_1709_09990_amd import tw as T
+    small = [G.gnp(18, 0.3, 9100), G.gnp(20, 0.25, 9102)]
+    graphs = [G.path(64), G.path(49), G.complete(5), small[0], G.edgeless(1), small[1]]
+    want = [1, 1, 4, oracle.subset_dp(small[0])[0], 0, oracle.subset_dp(small[1])[0]]
+    for sched in (T.TW_BATCH_ROUNDS, T.TW_BATCH_PERSISTENT):
+        with T.Context(device=0, batch_schedule=sched) as c:
+            tws, orders, status, _, per = c.solve_batch(graphs, graph_stats=True)
+        assert list(status) == [0] * len(graphs)
+        assert list(tws) == want
+        for rows, tw, order in zip(graphs, tws, orders):
+            assert oracle.order_width(rows, order) == tw
+        assert [q["path"] for q in per][:3] == [1, 1, 2]
