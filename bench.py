@@ -206,10 +206,24 @@ def cpu_baseline(budget_s: float = 15.0):
         cand_total += cand
         level += 1
     dt = time.perf_counter() - t0
+    cpu = ""
+    ram_gb = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram_gb = round(int(line.split()[1]) / 2**20, 1)
+                break
+    except OSError:
+        pass
     return {
         "value": cand_total / dt,
         "unit": "expansions/s",
         "cores": threads,
+        "host": {"cpu": cpu, "ram_gb": ram_gb},
         "kind": "oracle",
         "sample": f"levels 1..{level} of decide(k={k}) on the random partial 8-tree (n=40), "
                   f"{cand_total} (S,v) pairs in {dt:.1f} s",
