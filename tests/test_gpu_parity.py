@@ -460,3 +460,16 @@ def test_batch_mixed_sizes_up_to_64(oracle):
         for rows, tw, order in zip(graphs, tws, orders):
             assert oracle.order_width(rows, order) == tw
         assert [q["path"] for q in per][:3] == [1, 1, 2]
+
+
+def test_degenerate_inputs(ctx):
+    """An empty batch, the largest n (64) at its extreme bounds, a single vertex."""
+    tws, orders, status, st = ctx.solve_batch([])
+    assert len(tws) == 0 and len(status) == 0
+    K64 = G.complete(64)
+    assert ctx.decide(K64, 63)[0] is True      # k >= n - 1: YES with no level
+    assert ctx.decide(K64, 62)[0] is False     # one level of 64 states, none feasible
+    tw, order, _ = ctx.solve(K64)
+    assert tw == 63 and sorted(order) == list(range(64))
+    tw, order, _ = ctx.solve(G.edgeless(1))
+    assert tw == 0 and list(order) == [0]
