@@ -962,6 +962,14 @@ tw_status solve_one(tw_ctx *c, const Graph &g, const Reduction *red, int lb, int
     while (best_yes > known_no + 1) {
         int yes = 0;
         tw_status s = decide_checked(c, g, red, k, kKeepIfSmall, levels, &yes, rs);
+        if ((s == TW_ECAPACITY || s == TW_ENOMEM) && k > known_no + 1) {
+            // a bound above the ascending frontier (a learned start) outgrew the
+            // state cap or memory: continue upwards from the frontier instead
+            free_levels(c, levels);
+            c->err.clear();
+            k = known_no + 1;
+            continue;
+        }
         if (s != TW_OK) {
             free_levels(c, levels);
             return s;
