@@ -169,7 +169,9 @@ tw_status tw_solve(tw_ctx *ctx, const tw_graph *g, int32_t *out_tw, int32_t *out
  * With options.k_policy = TW_K_LEARNED each graph starts at the bound the
  * network predicts (clamped to [lower bound, n-2]) and gets an arena sized
  * from the predicted peak level; the search then certifies the answer exactly
- * (YES at t and NO at t-1, or t = lower bound).  out_graph_stats (nullable,
+ * (YES at t and NO at t-1, or t = lower bound).  A start above the ascending
+ * frontier whose levels exceed max_states or memory continues upwards from
+ * the frontier instead.  out_graph_stats (nullable,
  * [count]) receives per-graph outcomes.  A graph that fails gets its own
  * status; the others still complete.  The return value is TW_OK unless an
  * argument is invalid or the device failed. */
