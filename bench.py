@@ -248,7 +248,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the search over one graph "
-              "is not sharded across GPUs in this build", file=sys.stderr)
+              "is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
     from paper_1709_09990_amd import tw as T
