@@ -423,6 +423,20 @@ struct RunStats {
 };
 
 // Per-graph outcome of a search (start bound, certifying run's peak, work).
+void add_run_stats(RunStats &into, const RunStats &from)
+{
+    into.states_expanded += from.states_expanded;
+    into.expansions += from.expansions;
+    into.successors += from.successors;
+    into.unique += from.unique;
+    into.peak = std::max(into.peak, from.peak);
+    into.decisions += from.decisions;
+    into.levels += from.levels;
+    into.retries += from.retries;
+    into.launches += from.launches;
+    into.kernel_seconds += from.kernel_seconds;
+}
+
 struct GraphOutcome {
     uint64_t peak_yes = 0, expansions = 0, states = 0;
     int32_t start_k = 0;
@@ -1665,6 +1679,69 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
         batch_ids.swap(keep);
     }
     const std::vector<Reduction> *rp = c->opt.reductions ? &reds : nullptr;
+
+    // Graphs already bound for the single-graph path (above the batched size,
+    // Bloom dedup, or predicted too large for an arena) run on a second
+    // context and stream, concurrently with the batched search.
+    struct Aux {
+        tw_ctx *ctx = nullptr;
+        std::thread th;
+        RunStats rs;
+        tw_status status = TW_OK;
+        std::string err;
+        ~Aux()
+        {
+            if (th.joinable())
+                th.join();
+            if (ctx)
+                tw_ctx_destroy(ctx);
+        }
+    } aux;
+    if (!single_ids.empty() && !batch_ids.empty()) {
+        tw_options o = c->opt;
+        o.stream = nullptr;
+        o.k_policy = TW_K_ASCENDING;  // starts are already chosen
+        o.weights_path = nullptr;
+        if (tw_ctx_create(&o, &aux.ctx) == TW_OK) {
+            std::vector<int> early;
+            early.swap(single_ids);
+            aux.th = std::thread([&, early]() {
+                if (hipSetDevice(c->device) != hipSuccess) {
+                    aux.status = TW_EDEVICE;
+                    aux.err = "hipSetDevice failed on the second context";
+                    return;
+                }
+                for (int t : early) {
+                    GraphOutcome oc;
+                    tw_status s = solve_one(aux.ctx, graphs[(size_t)t], rp ? &reds[(size_t)t] : nullptr,
+                                            lbs[(size_t)t], k0s[(size_t)t], &out_tw[t],
+                                            out_orders + offs[(size_t)t], aux.rs, &oc);
+                    out_status[t] = s;
+                    if (s != TW_OK)
+                        out_tw[t] = -1;
+                    else
+                        outcomes[(size_t)t] = oc;
+                    if (s == TW_EDEVICE) {
+                        aux.status = s;
+                        aux.err = aux.ctx->err;
+                        return;
+                    }
+                }
+            });
+        } else {
+            aux.ctx = nullptr;  // no second context: they run below on this one
+        }
+    }
+    auto join_aux = [&]() -> tw_status {
+        if (aux.th.joinable())
+            aux.th.join();
+        add_run_stats(rs, aux.rs);
+        aux.rs = RunStats{};
+        if (aux.status != TW_OK)
+            return fail(c, aux.status, "%s", aux.err.c_str());
+        return TW_OK;
+    };
+
     const size_t before = single_ids.size();
     st = batch_run(c, graphs, rp, lbs, k0s, arena_of, batch_ids, out_tw, out_orders, offs, out_status,
                    single_ids, outcomes, rs);
@@ -1703,6 +1780,9 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
         if (s == TW_EDEVICE)
             return s;
     }
+    st = join_aux();
+    if (st != TW_OK)
+        return st;
     if (out_graph_stats)
         for (uint32_t t = 0; t < count; ++t) {
             tw_graph_stats &o = out_graph_stats[t];
