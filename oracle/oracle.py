@@ -24,6 +24,9 @@ Functions and their sources:
     brute_force         min over all orders of the fill-in width (§2)
     order_width         fill-in width of one order (§2)
     bfs_level / decide  Listing 1 (§3.1) with exact duplicate removal
+    eliminated_graph    H_S, the graph left after eliminating S (§2)
+    mmw_eliminated /    MMW(H_S) and the per-state pruning test of §3.3
+      mmw_keep
 """
 from __future__ import annotations
 
@@ -84,6 +87,15 @@ def lib():
         L.tworacle_count_feasible.restype = ctypes.c_int64
         L.tworacle_max_threads.argtypes = []
         L.tworacle_max_threads.restype = ctypes.c_int
+        L.tworacle_eliminated_graph.argtypes = [ctypes.c_int, u64p, ctypes.c_uint64, u64p]
+        L.tworacle_eliminated_graph.restype = ctypes.c_int
+        L.tworacle_mmw.argtypes = [ctypes.c_int, u64p]
+        L.tworacle_mmw.restype = ctypes.c_int
+        L.tworacle_mmw_eliminated.argtypes = [ctypes.c_int, u64p, ctypes.c_uint64]
+        L.tworacle_mmw_eliminated.restype = ctypes.c_int
+        L.tworacle_mmw_keep.argtypes = [ctypes.c_int, u64p, ctypes.c_int, u64p, ctypes.c_int64, u8p,
+                                        ctypes.c_int]
+        L.tworacle_mmw_keep.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -231,12 +243,15 @@ def bfs_level(rows, k: int, frontier: np.ndarray, threads: int = 0, allowed: int
     return out, gen.value, cand.value
 
 
-def decide(rows, k: int, keep_levels: bool = True, threads: int = 0, on_level=None):
+def decide(rows, k: int, keep_levels: bool = True, threads: int = 0, on_level=None,
+           prune_mmw: bool = False):
     """decide(k) by Listing 1: YES iff the last level is non-empty.
 
     Returns (yes, levels, stats) where levels = [F_0..F_L] (sorted arrays; only
     the counts when keep_levels is False) and stats holds per-level
-    (candidates E_i, feasible G_i)."""
+    (candidates E_i, feasible G_i).  With prune_mmw (O6, §3.3) a state S with
+    MMW(H_S) > k is not expanded: level i+1 holds the successors of the kept
+    states of level i (the stored levels themselves are not filtered)."""
     a = _rows(rows)
     n = len(a)
     L = n_levels(n, k)
@@ -244,6 +259,8 @@ def decide(rows, k: int, keep_levels: bool = True, threads: int = 0, on_level=No
     levels = [f if keep_levels else 1]
     stats = []
     for i in range(L):
+        if prune_mmw:
+            f = f[mmw_keep(a, k, f, threads)]
         nxt, gen, cand = bfs_level(a, k, f, threads)
         stats.append((cand, gen))
         if on_level is not None:
@@ -312,6 +329,43 @@ def mmw(rows) -> int:
                 nb[u].add(w)
         del nb[v]
     return lb
+
+
+# ---------------------------------------------------------------------------
+# O6: per-state minor-min-width (§3.3 on the graph left after eliminating S)
+# ---------------------------------------------------------------------------
+
+def eliminated_graph(rows, S: int) -> np.ndarray:
+    """Rows of H_S: row u = Q(S, u) for u outside S, 0 for u in S."""
+    a = _rows(rows)
+    out = np.zeros(len(a), dtype=np.uint64)
+    if lib().tworacle_eliminated_graph(len(a), _p(a, u64p), int(S), _p(out, u64p)) != 0:
+        raise ValueError("bad graph")
+    return out
+
+
+def mmw_c(rows) -> int:
+    """The C implementation of mmw (same rounds and tie-breaks)."""
+    a = _rows(rows)
+    return lib().tworacle_mmw(len(a), _p(a, u64p))
+
+
+def mmw_eliminated(rows, S: int) -> int:
+    """MMW(H_S), on the vertices outside S."""
+    a = _rows(rows)
+    return lib().tworacle_mmw_eliminated(len(a), _p(a, u64p), int(S))
+
+
+def mmw_keep(rows, k: int, states: np.ndarray, threads: int = 0) -> np.ndarray:
+    """Boolean mask: MMW(H_S) <= k for each state."""
+    a = _rows(rows)
+    s = np.ascontiguousarray(np.asarray(states, dtype=np.uint64))
+    keep = np.zeros(len(s), dtype=np.uint8)
+    if len(s):
+        r = lib().tworacle_mmw_keep(len(a), _p(a, u64p), int(k), _p(s, u64p), len(s), _p(keep, u8p), threads)
+        if r < 0:
+            raise ValueError("bad graph")
+    return keep.astype(bool)
 
 
 # ---------------------------------------------------------------------------

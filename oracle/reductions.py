@@ -135,11 +135,12 @@ def augmented_rows(rows, k: int, paths: np.ndarray | None = None) -> np.ndarray:
 
 
 def decide_reduced(rows, k: int, clique: list[int] | None = None, paths: np.ndarray | None = None,
-                   threads: int = 0):
+                   threads: int = 0, prune_mmw: bool = False):
     """decide(k) of Listing 1 on G_k+ with the clique's vertices never added.
 
     Returns (yes, levels): levels F_0..F_L(k) (sorted arrays) over subsets of
-    V minus C; ([F_0], NO) when k < |C| - 1."""
+    V minus C; ([F_0], NO) when k < |C| - 1.  With prune_mmw, states S whose
+    eliminated graph in G_k+ has MMW > k are not expanded (O6 of the C oracle)."""
     n = len(rows)
     C = max_clique(rows) if clique is None else clique
     if k < len(C) - 1:
@@ -149,6 +150,8 @@ def decide_reduced(rows, k: int, clique: list[int] | None = None, paths: np.ndar
     f = np.zeros(1, dtype=np.uint64)
     levels = [f]
     for _ in range(O.n_levels(n, k)):
+        if prune_mmw:
+            f = f[O.mmw_keep(rk, k, f, threads)]
         f, _, _ = O.bfs_level(rk, k, f, threads, allowed=allowed)
         levels.append(f)
         if len(f) == 0:

@@ -32,6 +32,15 @@
  *     degree |Q(S,v)| is at most k; duplicates are removed exactly (sort and
  *     unique, not a Bloom filter).
  *
+ *   - O6, per-state minor-min-width pruning (§3.3, applied to the graph that
+ *     remains once S is eliminated).  That graph H_S has vertex set V - S and
+ *     an edge uw exactly when w lies in Q(S, u) (§2).  MMW repeatedly records
+ *     the second-smallest degree, takes the lowest-index vertex of minimum
+ *     degree, deletes it if isolated and otherwise contracts it into its
+ *     lowest-index minimum-degree neighbour; the bound is the largest
+ *     recorded degree.  A state with MMW(H_S) > k cannot be completed within
+ *     width k and is not expanded.
+ *
  * Build: gcc -O2 -fopenmp -shared -fPIC -o libtworacle.so tw_oracle.c
  */
 #include <stdint.h>
@@ -438,4 +447,126 @@ int tworacle_max_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ---- O6: per-state minor-min-width ------------------------------------ */
+
+/* Q(S, v) as a vertex set, by the same depth-first search as q_degree. */
+static uint64_t q_set(const adjlist *g, uint64_t S, int v)
+{
+    unsigned char visited[MAXN];
+    int stack[MAXN];
+    int top = 0;
+    uint64_t q = 0;
+    memset(visited, 0, sizeof visited);
+    visited[v] = 1;
+    stack[top++] = v;
+    while (top > 0) {
+        int u = stack[--top];
+        for (int t = 0; t < g->deg[u]; t++) {
+            int w = g->nbr[u][t];
+            if (visited[w])
+                continue;
+            visited[w] = 1;
+            if ((S >> w) & 1ULL)
+                stack[top++] = w;
+            else
+                q |= 1ULL << w;
+        }
+    }
+    return q;
+}
+
+/* out[u] = Q(S, u) for u outside S, 0 for u in S: the rows of H_S. */
+int tworacle_eliminated_graph(int n, const uint64_t *rows, uint64_t S, uint64_t *out)
+{
+    adjlist g;
+    if (n < 1 || n > MAXN)
+        return -1;
+    build_lists(n, rows, &g);
+    for (int u = 0; u < n; u++)
+        out[u] = ((S >> u) & 1ULL) ? 0 : q_set(&g, S, u);
+    return 0;
+}
+
+/* MMW of the graph on the vertices of `alive` with neighbour sets nb[]
+ * (modified in place). */
+static int mmw_on(int n, uint64_t *nb, uint64_t alive)
+{
+    int lb = 0;
+    while (popcount64(alive) >= 2) {
+        int v = -1, d1 = MAXN + 1;
+        for (int u = 0; u < n; u++)
+            if (((alive >> u) & 1ULL) && popcount64(nb[u]) < d1) {
+                d1 = popcount64(nb[u]);
+                v = u;
+            }
+        int d2 = MAXN + 1;
+        for (int u = 0; u < n; u++)
+            if (u != v && ((alive >> u) & 1ULL) && popcount64(nb[u]) < d2)
+                d2 = popcount64(nb[u]);
+        if (d2 > lb)
+            lb = d2;
+        if (nb[v] == 0) {
+            alive &= ~(1ULL << v);
+            continue;
+        }
+        int c = -1, dc = MAXN + 1;
+        for (int w = 0; w < n; w++)
+            if (((nb[v] >> w) & 1ULL) && popcount64(nb[w]) < dc) {
+                dc = popcount64(nb[w]);
+                c = w;
+            }
+        /* contract v into c: c keeps its label and gains v's other neighbours */
+        for (int w = 0; w < n; w++) {
+            if (!((nb[v] >> w) & 1ULL))
+                continue;
+            nb[w] &= ~(1ULL << v);
+            if (w != c) {
+                nb[w] |= 1ULL << c;
+                nb[c] |= 1ULL << w;
+            }
+        }
+        nb[v] = 0;
+        alive &= ~(1ULL << v);
+    }
+    return lb;
+}
+
+int tworacle_mmw(int n, const uint64_t *rows)
+{
+    uint64_t nb[MAXN];
+    if (n < 1 || n > MAXN)
+        return -1;
+    memcpy(nb, rows, sizeof(uint64_t) * (size_t)n);
+    return mmw_on(n, nb, n == 64 ? ~0ULL : (1ULL << n) - 1);
+}
+
+/* MMW(H_S). */
+int tworacle_mmw_eliminated(int n, const uint64_t *rows, uint64_t S)
+{
+    uint64_t nb[MAXN];
+    if (tworacle_eliminated_graph(n, rows, S, nb) != 0)
+        return -1;
+    const uint64_t all = n == 64 ? ~0ULL : (1ULL << n) - 1;
+    return mmw_on(n, nb, all & ~S);
+}
+
+/* keep[s] = 1 iff MMW(H_S) <= k for S = states[s]; returns how many are kept. */
+int64_t tworacle_mmw_keep(int n, const uint64_t *rows, int k, const uint64_t *states, int64_t count,
+                          uint8_t *keep, int nthreads)
+{
+    if (n < 1 || n > MAXN)
+        return -1;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+    int64_t kept = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : kept)
+    for (int64_t s = 0; s < count; s++) {
+        keep[s] = tworacle_mmw_eliminated(n, rows, states[s]) <= k;
+        kept += keep[s];
+    }
+    return kept;
 }
