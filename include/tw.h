@@ -114,10 +114,20 @@ typedef struct {
                                  every non-adjacent pair joined by >= k + 1 internally vertex-disjoint
                                  paths in G (counts taken once per graph).  Answers are unchanged; levels
                                  become {S outside C : |S| = i, S has width <= k in that graph}. */
+    int mmw_prune;            /* TW_MMW_NONE (default), or TW_MMW_PRUNE: per-state minor-min-width (§3.3)
+                                 — before a level is expanded, every state S whose eliminated graph H_S
+                                 (vertices outside S, an edge uw when w lies in Q(S, u)) has minor-min-width
+                                 above k is dropped, since the remaining vertices cannot then be eliminated
+                                 within width k.  MMW as tw_mmw, on H_S.  Answers are unchanged; level i+1
+                                 holds the successors of the kept states of level i (levels handed to a
+                                 trace sink are the unpruned ones; the kept-state counts go to
+                                 tw_stats.states_expanded).  tw_solve_batch then solves every graph on the
+                                 tw_solve path. */
 } tw_options;
 
 enum { TW_REDUCE_NONE = 0, TW_REDUCE_CLIQUE_PATHS = 1 };
 enum { TW_BATCH_ROUNDS = 0, TW_BATCH_PERSISTENT = 1 };
+enum { TW_MMW_NONE = 0, TW_MMW_PRUNE = 1 };
 
 /* Counters of one call (summed over every bound k and level it ran). */
 typedef struct {

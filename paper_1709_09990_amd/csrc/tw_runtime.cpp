@@ -22,6 +22,7 @@
 
 #include "tw.h"
 #include "tw_probe.h"
+#include "tw_mmw.h"
 #include "tw_batch.h"
 #include "tw_internal.h"
 
@@ -500,6 +501,49 @@ tw_status emit_level(tw_ctx *c, const Sink &sink, int k, int i, const Level &lv,
     return TW_OK;
 }
 
+// Per-state minor-min-width pruning (§3.3): level `in` is replaced by its
+// states S with MMW(H_S) <= k (creating vertices kept alongside).  A dropped
+// state has no completion within width k, so no order is lost.
+tw_status prune_level(tw_ctx *c, Level &in, int n, int k, int kb, RunStats &rs)
+{
+    Buf keys, lastv;
+    tw_status s = acquire(c, keys, in.count * (uint64_t)kb);
+    if (s == TW_OK && in.lastv.p)
+        s = acquire(c, lastv, in.count);
+    if (s != TW_OK) {
+        release(c, keys);
+        return s;
+    }
+    HIP_TRY(c, twk::launch_zero_counters((LevelCounters *)c->d_ctr.p, c->stream));
+    twk::PruneArgs a{};
+    a.in = in.keys.p;
+    a.in_lastv = (const uint8_t *)in.lastv.p;
+    a.in_count = in.count;
+    a.out = keys.p;
+    a.out_lastv = (uint8_t *)lastv.p;
+    a.adj = (const uint64_t *)c->d_adj.p;
+    a.kept = &((LevelCounters *)c->d_ctr.p)->out_count;
+    a.n = n;
+    a.k = k;
+    a.key_bytes = kb;
+    const uint64_t waves = (in.count + 63) / 64;
+    uint64_t blocks = (waves + twk::kWavesPerBlock - 1) / twk::kWavesPerBlock;
+    blocks = std::min<uint64_t>(std::max<uint64_t>(blocks, 1), (uint64_t)c->cu_count * 8);
+    HIP_TRY(c, twk::launch_mmw_prune(a, (unsigned)blocks, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr.p, sizeof(LevelCounters), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const uint64_t kept = c->h_ctr->out_count;
+    if (kept > in.count)
+        return fail(c, TW_EDEVICE, "pruning kept %llu of %llu states", (unsigned long long)kept,
+                    (unsigned long long)in.count);
+    release(c, in.keys);
+    release(c, in.lastv);
+    in.keys = keys;
+    in.lastv = lastv;
+    in.count = kept;
+    return TW_OK;
+}
+
 // Level retention of run_decide.
 enum Keep {
     kKeepPair = 0,     // only the current pair; levels.back() is the last level reached
@@ -561,6 +605,15 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, int keep, const Sink *sin
 
     for (; i < L; ++i) {
         Level &in = levels.back();
+        if (c->opt.mmw_prune == TW_MMW_PRUNE && in.count) {
+            status = prune_level(c, in, n, k, kb, rs);
+            if (status != TW_OK)
+                goto done;
+            if (in.count == 0) {
+                cur = 0;
+                break;
+            }
+        }
         const uint64_t in_count = in.count;
         const bool bloom = c->opt.dedup == TW_DEDUP_BLOOM || c->opt.dedup == TW_DEDUP_BLOOM_CERTIFIED;
         // every new state comes from a distinct (S, v) pair; exact dedup also
@@ -1403,7 +1456,8 @@ tw_status tw_ctx_create(const tw_options *options, tw_ctx **out)
     if ((c->opt.dedup != TW_DEDUP_EXACT && c->opt.dedup != TW_DEDUP_BLOOM &&
          c->opt.dedup != TW_DEDUP_BLOOM_CERTIFIED) ||
         (c->opt.reductions != TW_REDUCE_NONE && c->opt.reductions != TW_REDUCE_CLIQUE_PATHS) ||
-        (c->opt.batch_schedule != TW_BATCH_ROUNDS && c->opt.batch_schedule != TW_BATCH_PERSISTENT)) {
+        (c->opt.batch_schedule != TW_BATCH_ROUNDS && c->opt.batch_schedule != TW_BATCH_PERSISTENT) ||
+        (c->opt.mmw_prune != TW_MMW_NONE && c->opt.mmw_prune != TW_MMW_PRUNE)) {
         delete c;
         return TW_EINVAL;
     }
@@ -1652,7 +1706,7 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
                 out_orders[offs[t] + v] = v;
             outcomes[t].start_k = g.n - 1;
             outcomes[t].path = 2;
-        } else if (g.n <= twk::kBatchMaxN && c->opt.dedup == TW_DEDUP_EXACT) {
+        } else if (g.n <= twk::kBatchMaxN && c->opt.dedup == TW_DEDUP_EXACT && c->opt.mmw_prune == TW_MMW_NONE) {
             batch_ids.push_back((int)t);
         } else {
             single_ids.push_back((int)t);

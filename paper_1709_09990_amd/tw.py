@@ -20,6 +20,7 @@ TW_DEDUP_EXACT, TW_DEDUP_BLOOM, TW_DEDUP_BLOOM_CERTIFIED = 0, 1, 2
 TW_K_ASCENDING, TW_K_LEARNED = 0, 1
 TW_REDUCE_NONE, TW_REDUCE_CLIQUE_PATHS = 0, 1
 TW_BATCH_ROUNDS, TW_BATCH_PERSISTENT = 0, 1
+TW_MMW_NONE, TW_MMW_PRUNE = 0, 1
 
 
 class TwError(RuntimeError):
@@ -50,6 +51,7 @@ class _Options(ctypes.Structure):
         ("batch_chunk", ctypes.c_uint32),
         ("batch_schedule", ctypes.c_int),
         ("reductions", ctypes.c_int),
+        ("mmw_prune", ctypes.c_int),
     ]
 
 
@@ -251,7 +253,8 @@ class Context:
                  load_factor: float = 0.0, max_states: int = 0, capacity_override: int = 0,
                  timing: bool = False, k_policy: int = TW_K_ASCENDING, weights_path: str | None = None,
                  batch_graph_states: int = 0, batch_chunk: int = 0, probe: int = 0, partition: int = 0,
-                 reductions: int = TW_REDUCE_NONE, batch_schedule: int = TW_BATCH_ROUNDS):
+                 reductions: int = TW_REDUCE_NONE, batch_schedule: int = TW_BATCH_ROUNDS,
+                 mmw_prune: int = TW_MMW_NONE):
         L = load()
         self._L = L
         o = _Options()
@@ -271,6 +274,7 @@ class Context:
         o.batch_graph_states = batch_graph_states
         o.batch_chunk = batch_chunk
         o.reductions = reductions
+        o.mmw_prune = mmw_prune
         o.batch_schedule = batch_schedule
         h = ctypes.c_void_p()
         st = L.tw_ctx_create(ctypes.byref(o), ctypes.byref(h))

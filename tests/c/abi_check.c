@@ -11,6 +11,7 @@ int main(void)
 {
     printf("sizeof_options %zu\n", sizeof(tw_options));
     printf("off_reductions %zu\n", offsetof(tw_options, reductions));
+    printf("off_mmw_prune %zu\n", offsetof(tw_options, mmw_prune));
     printf("off_batch_schedule %zu\n", offsetof(tw_options, batch_schedule));
     printf("off_batch_chunk %zu\n", offsetof(tw_options, batch_chunk));
     printf("sizeof_stats %zu\n", sizeof(tw_stats));

@@ -37,7 +37,7 @@ def c_program(tmp_path_factory):
 def test_struct_layouts_match_binding(c_program):
     f = c_program
     assert int(f["sizeof_options"][0]) == ctypes.sizeof(T._Options)
-    for name in ("reductions", "batch_schedule", "batch_chunk"):
+    for name in ("mmw_prune", "reductions", "batch_schedule", "batch_chunk"):
         assert int(f["off_" + name][0]) == getattr(T._Options, name).offset, name
     assert int(f["sizeof_stats"][0]) == ctypes.sizeof(T._Stats)
     assert int(f["sizeof_graph_stats"][0]) == ctypes.sizeof(T._GraphStats)
