@@ -182,6 +182,31 @@ def reductions_leg(graphs: dict, steps: int = 2) -> dict:
     return out
 
 
+def mmw_leg(graphs: dict, steps: int = 1) -> dict:
+    """The same single-graph solves with per-state minor-min-width pruning
+    (§3.3, TW_MMW_PRUNE): time per step, states expanded, answers checked
+    against the plain search's."""
+    from paper_1709_09990_amd import tw as T
+    out = {}
+    with T.Context(device=0, timing=True, mmw_prune=T.TW_MMW_PRUNE) as c:
+        c.solve(graphs[min(graphs, key=lambda nm: len(graphs[nm]))])  # warm
+        t0 = time.perf_counter()
+        states = exp_kernel = 0
+        tws = {}
+        for _ in range(steps):
+            for nm in graphs:
+                tw, _, st = c.solve(graphs[nm])
+                tws[nm] = tw
+                states += st["states_expanded"]
+                exp_kernel += st["kernel_seconds"]
+        dt = time.perf_counter() - t0
+    out["ms_per_step"] = dt / steps * 1e3
+    out["states_expanded_per_step"] = states // steps
+    out["expansion_kernel_ms_per_step"] = exp_kernel / steps * 1e3
+    out["treewidth"] = tws
+    return out
+
+
 def cpu_baseline(budget_s: float = 15.0):
     """The oracle timed on a bounded prefix: levels of decide(8) on the random
     partial 8-tree (n=40) until the budget is spent."""
@@ -242,6 +267,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched learned-vs-plain leg")
     ap.add_argument("--no-probe", action="store_true", help="skip the random-access reference measurement")
     ap.add_argument("--no-reduce", action="store_true", help="skip the single-graph leg with the section 3.1 reductions")
+    ap.add_argument("--mmw", action="store_true", help="add a single-graph leg with per-state minor-min-width pruning")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -342,6 +368,13 @@ def main():
         r["speedup_vs_plain_step"] = round(out["ms_per_step"] / r["ms_per_step"], 3)
         r["expansions_plain_per_step"] = total["expansions"] // args.steps
         out["reductions"] = r
+    if args.mmw:
+        m = mmw_leg(graphs)
+        if m["treewidth"] != tws:
+            raise RuntimeError(f"pruning changed an answer: {m['treewidth']} vs {tws}")
+        m["slowdown_vs_plain_step"] = round(m["ms_per_step"] / out["ms_per_step"], 3)
+        m["states_expanded_plain_per_step"] = total["states_expanded"] // args.steps
+        out["mmw_prune"] = m
     if not args.no_batch:
         out["batch"] = batch_leg()
     if not args.no_cpu:
