@@ -13,8 +13,8 @@
 // the lowest-index vertex v of minimum degree; delete it if isolated, else
 // contract it into its lowest-index minimum-degree neighbour u (u keeps its
 // label and gains v's other neighbours).  A state is dropped as soon as a
-// recorded degree exceeds k; rounds stop once at most k + 1 vertices remain,
-// since no degree there can exceed k.
+// round's second-smallest degree exceeds k; rounds stop once at most k + 1
+// vertices remain, since no degree there can exceed k.
 #include "tw_mmw.h"
 #include "tw_wave.h"
 
