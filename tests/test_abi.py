@@ -124,3 +124,13 @@ def test_tree_decomposition_from_orders(oracle):
             assert oracle.is_tree_decomposition(rows, bags, parent)
     with pytest.raises(T.TwError):
         T.tree_decomposition(G.path(3), [0, 0, 1])
+
+
+def test_invalid_options_rejected_before_any_device_call():
+    """tw_ctx_create validates the option enums before touching a device, so
+    a bad value is TW_EINVAL even on a machine without a GPU."""
+    bad = [dict(dedup=7), dict(reductions=3), dict(batch_schedule=4), dict(mmw_prune=2), dict(mmw_prune=-1)]
+    for kw in bad:
+        with pytest.raises(T.TwError) as e:
+            T.Context(device=0, **kw)
+        assert e.value.status == T.TW_EINVAL, kw
