@@ -79,6 +79,10 @@ def lib():
         L.tworacle_bfs_level_masked.argtypes = [ctypes.c_int, u64p, ctypes.c_int, ctypes.c_uint64, u64p,
                                                 ctypes.c_int64, ctypes.POINTER(u64p), i64p, i64p, ctypes.c_int]
         L.tworacle_bfs_level_masked.restype = ctypes.c_int64
+        L.tworacle_bfs_level_part.argtypes = [ctypes.c_int, u64p, ctypes.c_int, ctypes.c_uint64, u64p,
+                                              ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(u64p),
+                                              i64p, i64p, ctypes.c_int]
+        L.tworacle_bfs_level_part.restype = ctypes.c_int64
         L.tworacle_free.argtypes = [ctypes.c_void_p]
         L.tworacle_free.restype = None
         L.tworacle_bfs_level.restype = ctypes.c_int64
@@ -217,30 +221,43 @@ def frontiers_from_dp(rows, k: int, table: np.ndarray | None = None) -> list[np.
 # O4: the level search of Listing 1 with exact duplicate removal
 # ---------------------------------------------------------------------------
 
-def bfs_level(rows, k: int, frontier: np.ndarray, threads: int = 0, allowed: int | None = None):
+def bfs_level(rows, k: int, frontier: np.ndarray, threads: int = 0, allowed: int | None = None,
+              parts: int = 1, part: int = 0):
     """One level: returns (next frontier sorted, feasible pairs, candidate pairs).
-    With `allowed`, only those vertices may be added (candidates count only them)."""
+    With `allowed`, only those vertices may be added (candidates count only them).
+    With parts > 1 (a power of two), only the successors of group `part` of
+    `parts` (a fixed function of the successor key) and their pairs."""
     a = _rows(rows)
     n = len(a)
     f = np.ascontiguousarray(np.asarray(frontier, dtype=np.uint64))
     ptr = u64p()
     gen = ctypes.c_int64(0)
     cand = ctypes.c_int64(0)
+    mask = (2**64 - 1) if allowed is None else int(allowed) & (2**64 - 1)
     L = lib()
-    if allowed is None:
-        cnt = L.tworacle_bfs_level(n, _p(a, u64p), int(k), _p(f, u64p), len(f), ctypes.byref(ptr),
-                                   ctypes.byref(gen), ctypes.byref(cand), threads)
-    else:
-        cnt = L.tworacle_bfs_level_masked(n, _p(a, u64p), int(k), int(allowed) & (2**64 - 1), _p(f, u64p),
-                                          len(f), ctypes.byref(ptr), ctypes.byref(gen), ctypes.byref(cand),
-                                          threads)
+    cnt = L.tworacle_bfs_level_part(n, _p(a, u64p), int(k), mask, _p(f, u64p), len(f), int(parts),
+                                    int(part), ctypes.byref(ptr), ctypes.byref(gen), ctypes.byref(cand),
+                                    threads)
     if cnt < 0:
-        raise RuntimeError("oracle bfs_level failed (out of memory?)")
+        raise RuntimeError("oracle bfs_level failed (bad argument or out of memory)")
     try:
         out = np.ctypeslib.as_array(ptr, shape=(cnt,)).copy() if cnt else np.zeros(0, dtype=np.uint64)
     finally:
         L.tworacle_free(ptr)
     return out, gen.value, cand.value
+
+
+def bfs_level_grouped(rows, k: int, frontier: np.ndarray, parts: int, threads: int = 0):
+    """One level built group by group (bounded memory): returns (next level,
+    unsorted across groups, feasible pairs, candidate pairs)."""
+    outs, gen, cand = [], 0, 0
+    for p in range(parts):
+        o, g, c = bfs_level(rows, k, frontier, threads, parts=parts, part=p)
+        outs.append(o)
+        gen += g
+        cand += c
+    nxt = np.concatenate(outs) if outs else np.zeros(0, dtype=np.uint64)
+    return nxt, gen, cand
 
 
 def decide(rows, k: int, keep_levels: bool = True, threads: int = 0, on_level=None,

@@ -8,12 +8,12 @@
  *
  * Everything here is deliberately plain and slow:
  *
- *   - Q(S,v) and its size follow the definition in §2 (Preliminaries): the
- *     vertices outside S that v reaches by paths whose internal vertices all
- *     lie in S.  The size is computed by the stack-based depth-first search of
- *     Listing 1 (§3.1) over adjacency lists, with v itself marked visited
- *     before the search starts so it is never counted (reading: v is not a
- *     member of Q(S,v)).
+ *   - Q(S,v) follows the definition in §2 (Preliminaries): the vertices
+ *     outside S, other than v, that v reaches by paths whose internal
+ *     vertices all lie in S.  It is computed as a closure on vertex sets:
+ *     start from the neighbours of v; whenever a vertex of S is in the set,
+ *     add its neighbours; stop when nothing changes; then drop S and v
+ *     (reading: v is not a member of Q(S,v)).
  *
  *   - O1, the subset dynamic programme (§1 and §2: eliminating a set S gives
  *     the same intermediate graph whatever the order, so a Held-Karp style
@@ -52,57 +52,35 @@
 
 #define MAXN 64
 
-typedef struct {
-    int n;
-    int deg[MAXN];
-    int nbr[MAXN][MAXN]; /* adjacency lists, ascending */
-} adjlist;
-
-static void build_lists(int n, const uint64_t *rows, adjlist *g)
+/* Q(S,v) of §2 as a vertex set.  `reach` collects every vertex joined to v
+ * by a path whose internal vertices lie in S: the neighbours of v, and the
+ * neighbours of every vertex of S already collected.  `spent` marks the
+ * vertices of S whose neighbours were added.  v must lie outside S. */
+static uint64_t q_set(const uint64_t *rows, uint64_t S, int v)
 {
-    g->n = n;
-    for (int u = 0; u < n; u++) {
-        g->deg[u] = 0;
-        for (int w = 0; w < n; w++)
-            if ((rows[u] >> w) & 1ULL)
-                g->nbr[u][g->deg[u]++] = w;
+    uint64_t reach = rows[v];
+    uint64_t spent = 0;
+    for (;;) {
+        uint64_t open = reach & S & ~spent;
+        if (!open)
+            break;
+        int u = __builtin_ctzll(open);
+        spent |= 1ULL << u;
+        reach |= rows[u];
     }
+    return reach & ~S & ~(1ULL << v);
 }
 
-/* |Q(S,v)| by the depth-first search of Listing 1 (§3.1).  v must lie outside
- * S.  Vertices of S that are reached are pushed and explored further; every
- * other newly reached vertex is counted once. */
-static int q_degree(const adjlist *g, uint64_t S, int v)
+static int q_degree(const uint64_t *rows, uint64_t S, int v)
 {
-    unsigned char visited[MAXN];
-    int stack[MAXN];
-    int top = 0, degree = 0;
-    memset(visited, 0, sizeof visited);
-    visited[v] = 1;
-    stack[top++] = v;
-    while (top > 0) {
-        int u = stack[--top];
-        for (int t = 0; t < g->deg[u]; t++) {
-            int w = g->nbr[u][t];
-            if (visited[w])
-                continue;
-            visited[w] = 1;
-            if ((S >> w) & 1ULL)
-                stack[top++] = w;
-            else
-                degree++;
-        }
-    }
-    return degree;
+    return __builtin_popcountll(q_set(rows, S, v));
 }
 
 int tworacle_q_degree(int n, const uint64_t *rows, uint64_t S, int v)
 {
-    adjlist g;
     if (n < 1 || n > MAXN || v < 0 || v >= n || ((S >> v) & 1ULL))
         return -1;
-    build_lists(n, rows, &g);
-    return q_degree(&g, S, v);
+    return q_degree(rows, S, v);
 }
 
 static int popcount64(uint64_t x)
@@ -120,10 +98,8 @@ static int popcount64(uint64_t x)
  * entry depends only on the previous one, so those entries are independent. */
 int tworacle_subset_dp(int n, const uint64_t *rows, uint8_t *tw_table, int nthreads)
 {
-    adjlist g;
     if (n < 1 || n > 30)
         return -1;
-    build_lists(n, rows, &g);
     const int64_t total = (int64_t)1 << n;
     tw_table[0] = 0;
 #ifdef _OPENMP
@@ -140,7 +116,7 @@ int tworacle_subset_dp(int n, const uint64_t *rows, uint8_t *tw_table, int nthre
                 if (!(((uint64_t)S >> v) & 1ULL))
                     continue;
                 uint64_t R = (uint64_t)S & ~(1ULL << v);
-                int d = q_degree(&g, R, v);
+                int d = q_degree(rows, R, v);
                 int w = tw_table[R] > d ? tw_table[R] : d;
                 if (w < best)
                     best = w;
@@ -291,26 +267,39 @@ static void radix_sort(uint64_t *a, uint64_t *tmp, int64_t cnt)
     }
 }
 
-/* O4, one level of Listing 1 (§3.1) for the bound k: every S of in[] is
- * extended by every v outside S with |Q(S,v)| <= k; the successors are sorted
- * and duplicates removed.  *out receives a malloc'd array (free it with
- * tworacle_free) of the distinct successors in ascending order.  Returns their
- * number, or -1 on a bad argument or allocation failure.  *generated
- * (nullable) receives the number of feasible (S,v) pairs, *candidates
- * (nullable) the number of (S,v) pairs tried. */
-/* One level of Listing 1 where only vertices in `allowed` may be added to a
- * state (all vertices: the plain search; the complement of a maximum clique:
- * the first optimisation of §3.1, which never picks a clique vertex because
- * some optimal order eliminates the clique last). */
-int64_t tworacle_bfs_level_masked(int n, const uint64_t *rows, int k, uint64_t allowed,
-                                  const uint64_t *in, int64_t in_count, uint64_t **out,
-                                  int64_t *generated, int64_t *candidates, int nthreads)
+/* Which of `nparts` (a power of two) classes a successor key falls in:
+ * three 21-bit pieces of the key folded by xor, low bits taken.  Only used to
+ * split one level's successors into groups that are deduplicated one at a
+ * time; equal keys always land in the same group. */
+static int key_part(uint64_t key, int nparts)
 {
-    adjlist g;
-    if (n < 1 || n > MAXN || in_count < 0)
+    return (int)((key ^ (key >> 21) ^ (key >> 42)) & (uint64_t)(nparts - 1));
+}
+
+/* O4, one level of Listing 1 (§3.1) for the bound k: every S of in[] is
+ * extended by every v of `allowed` outside S with |Q(S,v)| <= k; the
+ * successors are sorted and duplicates removed.  Only vertices in `allowed`
+ * may be added (all vertices: the plain search; the complement of a maximum
+ * clique: the first optimisation of §3.1, which never picks a clique vertex
+ * because some optimal order eliminates the clique last).
+ *
+ * With nparts > 1 only the successors whose key_part is `part` are produced
+ * (and only their pairs counted), so a level too large for memory is built
+ * group by group; the groups of one level are disjoint and together give the
+ * whole level.
+ *
+ * *out receives a malloc'd array (free it with tworacle_free) of the distinct
+ * successors in ascending order.  Returns their number, or -1 on a bad
+ * argument or allocation failure.  *generated (nullable) receives the number
+ * of feasible (S,v) pairs, *candidates (nullable) the number of (S,v) pairs
+ * tried. */
+int64_t tworacle_bfs_level_part(int n, const uint64_t *rows, int k, uint64_t allowed,
+                                const uint64_t *in, int64_t in_count, int nparts, int part,
+                                uint64_t **out, int64_t *generated, int64_t *candidates, int nthreads)
+{
+    if (n < 1 || n > MAXN || in_count < 0 || nparts < 1 || (nparts & (nparts - 1)) != 0 ||
+        part < 0 || part >= nparts)
         return -1;
-    build_lists(n, rows, &g);
-    const uint64_t all = n == 64 ? ~0ULL : ((1ULL << n) - 1);
 #ifdef _OPENMP
     if (nthreads > 0)
         omp_set_num_threads(nthreads);
@@ -336,10 +325,13 @@ int64_t tworacle_bfs_level_masked(int n, const uint64_t *rows, int k, uint64_t a
             for (int v = 0; v < n; v++) {
                 if (((S >> v) & 1ULL) || !((allowed >> v) & 1ULL))
                     continue;
+                uint64_t key = S | (1ULL << v);
+                if (nparts > 1 && key_part(key, nparts) != part)
+                    continue;
                 tried[tid]++;
-                if (q_degree(&g, S, v) <= k) {
+                if (q_degree(rows, S, v) <= k) {
                     if (len[tid] == capb[tid]) {
-                        int64_t nc = capb[tid] ? capb[tid] * 2 : 4096;
+                        int64_t nc = capb[tid] ? capb[tid] + capb[tid] / 2 : 4096;
                         uint64_t *nb = realloc(buf[tid], (size_t)nc * sizeof(uint64_t));
                         if (!nb) {
                             fail = 1;
@@ -348,7 +340,7 @@ int64_t tworacle_bfs_level_masked(int n, const uint64_t *rows, int k, uint64_t a
                         buf[tid] = nb;
                         capb[tid] = nc;
                     }
-                    buf[tid][len[tid]++] = (S | (1ULL << v)) & all;
+                    buf[tid][len[tid]++] = key;
                 }
             }
         }
@@ -360,11 +352,9 @@ int64_t tworacle_bfs_level_masked(int n, const uint64_t *rows, int k, uint64_t a
     }
     int64_t result = -1;
     uint64_t *all_keys = NULL, *tmp = NULL;
-    if (!fail) {
+    if (!fail)
         all_keys = malloc((size_t)(total ? total : 1) * sizeof(uint64_t));
-        tmp = malloc((size_t)(total ? total : 1) * sizeof(uint64_t));
-    }
-    if (all_keys && tmp) {
+    if (all_keys) {
         int64_t pos = 0;
         for (int t = 0; t < nt; t++) {
             if (len[t])
@@ -373,6 +363,9 @@ int64_t tworacle_bfs_level_masked(int n, const uint64_t *rows, int k, uint64_t a
             free(buf[t]);
             buf[t] = NULL;
         }
+        tmp = malloc((size_t)(total ? total : 1) * sizeof(uint64_t));
+    }
+    if (all_keys && tmp) {
         radix_sort(all_keys, tmp, total);
         int64_t u = 0;
         for (int64_t t = 0; t < total; t++)
@@ -397,12 +390,20 @@ int64_t tworacle_bfs_level_masked(int n, const uint64_t *rows, int k, uint64_t a
     return result;
 }
 
+int64_t tworacle_bfs_level_masked(int n, const uint64_t *rows, int k, uint64_t allowed,
+                                  const uint64_t *in, int64_t in_count, uint64_t **out,
+                                  int64_t *generated, int64_t *candidates, int nthreads)
+{
+    return tworacle_bfs_level_part(n, rows, k, allowed, in, in_count, 1, 0, out, generated, candidates,
+                                   nthreads);
+}
+
 int64_t tworacle_bfs_level(int n, const uint64_t *rows, int k, const uint64_t *in,
                            int64_t in_count, uint64_t **out,
                            int64_t *generated, int64_t *candidates, int nthreads)
 {
-    return tworacle_bfs_level_masked(n, rows, k, ~0ULL, in, in_count, out, generated, candidates,
-                                     nthreads);
+    return tworacle_bfs_level_part(n, rows, k, ~0ULL, in, in_count, 1, 0, out, generated, candidates,
+                                   nthreads);
 }
 
 void tworacle_free(void *p)
@@ -415,10 +416,8 @@ void tworacle_free(void *p)
 int64_t tworacle_count_feasible(int n, const uint64_t *rows, int k, const uint64_t *in,
                                 int64_t in_count, int64_t *candidates, int nthreads)
 {
-    adjlist g;
     if (n < 1 || n > MAXN)
         return -1;
-    build_lists(n, rows, &g);
 #ifdef _OPENMP
     if (nthreads > 0)
         omp_set_num_threads(nthreads);
@@ -431,7 +430,7 @@ int64_t tworacle_count_feasible(int n, const uint64_t *rows, int k, const uint64
             if ((S >> v) & 1ULL)
                 continue;
             tried++;
-            if (q_degree(&g, S, v) <= k)
+            if (q_degree(rows, S, v) <= k)
                 feas++;
         }
     }
@@ -451,41 +450,13 @@ int tworacle_max_threads(void)
 
 /* ---- O6: per-state minor-min-width ------------------------------------ */
 
-/* Q(S, v) as a vertex set, by the same depth-first search as q_degree. */
-static uint64_t q_set(const adjlist *g, uint64_t S, int v)
-{
-    unsigned char visited[MAXN];
-    int stack[MAXN];
-    int top = 0;
-    uint64_t q = 0;
-    memset(visited, 0, sizeof visited);
-    visited[v] = 1;
-    stack[top++] = v;
-    while (top > 0) {
-        int u = stack[--top];
-        for (int t = 0; t < g->deg[u]; t++) {
-            int w = g->nbr[u][t];
-            if (visited[w])
-                continue;
-            visited[w] = 1;
-            if ((S >> w) & 1ULL)
-                stack[top++] = w;
-            else
-                q |= 1ULL << w;
-        }
-    }
-    return q;
-}
-
 /* out[u] = Q(S, u) for u outside S, 0 for u in S: the rows of H_S. */
 int tworacle_eliminated_graph(int n, const uint64_t *rows, uint64_t S, uint64_t *out)
 {
-    adjlist g;
     if (n < 1 || n > MAXN)
         return -1;
-    build_lists(n, rows, &g);
     for (int u = 0; u < n; u++)
-        out[u] = ((S >> u) & 1ULL) ? 0 : q_set(&g, S, u);
+        out[u] = ((S >> u) & 1ULL) ? 0 : q_set(rows, S, u);
     return 0;
 }
 
