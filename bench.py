@@ -158,6 +158,193 @@ def batch_leg(count: int = 512):
     return out
 
 
+def config1_leg(count: int = 64, reps: int = 3, oracle_graphs: int = 8) -> dict:
+    """Small single graphs: G(20, 0.3) with seeds 1001.., plain tw_solve
+    (ascending bounds from the minor-min-width bound).  Time per solve with
+    each bound's level loop replayed as one captured HIP graph, against the
+    host-driven loop (a launch sequence and a host wait per level); answers
+    must agree.  Beside it the oracle on the first graphs, on one core (the
+    paper's CPU baseline is sequential) and on every core: the subset DP over
+    all 2^20 sets, and the level search of Listing 1 from the same bound."""
+    from oracle import oracle as O
+    from paper_1709_09990_amd import graphs as G
+    from paper_1709_09990_amd import tw as T
+    import numpy as np
+    graphs = [G.workload_single_small(1001 + t) for t in range(count)]
+    out = {"graphs": count, "n": 20, "p": 0.3, "seeds": [1001, 1000 + count], "reps": reps}
+    ref = None
+    for name, cap in (("captured", T.TW_CAPTURE_AUTO), ("host_loop", T.TW_CAPTURE_OFF)):
+        with T.Context(device=0, capture=cap) as c:
+            for r in graphs[:4]:
+                c.solve(r)
+            exp = launches = levels = 0
+            tws = []
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                tws = []
+                for r in graphs:
+                    tw, _, st = c.solve(r)
+                    tws.append(tw)
+                    exp += st["expansions"]
+                    launches += st["launches"]
+                    levels += st["levels"]
+            dt = time.perf_counter() - t0
+        solves = count * reps
+        out[f"{name}_ms_per_solve"] = round(dt / solves * 1e3, 4)
+        out[f"{name}_solves_per_s"] = round(solves / dt, 1)
+        out[f"{name}_expansions_per_s"] = exp / dt
+        out[f"{name}_launches_per_solve"] = round(launches / solves, 2)
+        out[f"{name}_levels_per_solve"] = round(levels / solves, 2)
+        if ref is None:
+            ref = tws
+        elif ref != tws:
+            raise RuntimeError("config-1 leg: the captured loop changed an answer")
+    out["capture_speedup"] = round(out["host_loop_ms_per_solve"] / out["captured_ms_per_solve"], 3)
+    threads = O.max_threads()
+    try:
+        threads = min(threads, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        pass
+    sample = graphs[:oracle_graphs]
+    for label, th in (("1_core", 1), (f"{threads}_cores", threads)):
+        t0 = time.perf_counter()
+        for r, tw in zip(sample, ref):
+            got, _ = O.subset_dp(r, threads=th)
+            if got != tw:
+                raise RuntimeError("config-1 leg: the subset DP disagrees")
+        dt = time.perf_counter() - t0
+        out[f"oracle_subset_dp_{label}_ms_per_graph"] = round(dt / len(sample) * 1e3, 2)
+        t0 = time.perf_counter()
+        for r, tw in zip(sample, ref):
+            if O.treewidth_bfs(r, O.mmw(r), threads=th) != tw:
+                raise RuntimeError("config-1 leg: the oracle level search disagrees")
+        dt = time.perf_counter() - t0
+        out[f"oracle_level_search_{label}_ms_per_graph"] = round(dt / len(sample) * 1e3, 2)
+    out["oracle_graphs"] = len(sample)
+    out["oracle_cores"] = threads
+    out["treewidths"] = sorted(set(int(x) for x in np.asarray(ref)))
+    return out
+
+
+WEIGHTS_N40_REDUCED = os.path.join(ROOT, "paper_1709_09990_amd", "weights", "mpnn_mixture_n16_40_reduced.bin")
+
+
+def _outcomes(graphs, tws, status, per) -> dict:
+    import numpy as np
+    solved = [t for t in range(len(graphs)) if status[t] == 0]
+    failed = [t for t in range(len(graphs)) if status[t] != 0]
+    codes = {}
+    for t in failed:
+        codes[int(status[t])] = codes.get(int(status[t]), 0) + 1
+    out = {"solved": len(solved), "unsolved": len(failed), "unsolved_status": codes}
+    if failed:
+        ns = [len(graphs[t]) for t in failed]
+        peaks = [int(per[t]["peak_any"]) for t in failed]
+        out["unsolved_n_range"] = [min(ns), max(ns)]
+        out["unsolved_largest_level_min"] = min(peaks)
+        out["unsolved_graphs"] = [[t, len(graphs[t]), int(per[t]["peak_any"])] for t in failed]
+    out["paths"] = {str(p): sum(1 for t in range(len(graphs)) if per[t]["path"] == p) for p in (0, 1, 2)}
+    return out
+
+
+def batch_config_leg(graphs, label: str, max_states: int, weights: str, reductions: bool,
+                     ceiling: bool = False) -> dict:
+    """Graphs solved per second, plain ascending bounds against the learned
+    start bound, on one batch, each graph's levels capped at max_states
+    states (a graph whose level would exceed the cap returns TW_ECAPACITY with
+    the size it reached).  Batch options from the autotuner (tuned on the
+    batch's graphs of n <= 32).  Answers must agree on every graph both
+    policies solve.  With ceiling: the certifying work alone (decide(tw) and,
+    when tw is above the lower bound, decide(tw - 1)) per solved graph, i.e.
+    a start bound that is never wrong."""
+    import numpy as np
+    from paper_1709_09990_amd import autotune
+    from paper_1709_09990_amd import tw as T
+    small = [g for g in graphs if len(g) <= 32][:48]
+    tuned = autotune.tuned_options(small, sample=48) if small else {}
+    base = dict(tuned)
+    base["max_states"] = max_states
+    if reductions:
+        base["reductions"] = T.TW_REDUCE_CLIQUE_PATHS
+    out = {"label": label, "graphs": len(graphs), "n": [min(len(g) for g in graphs), max(len(g) for g in graphs)],
+           "max_states_per_level": max_states, "reductions": reductions, "tuned_options": tuned,
+           "weights": os.path.relpath(weights, ROOT)}
+    res = {}
+    for name, kw in (("plain", {}), ("learned", {"k_policy": T.TW_K_LEARNED, "weights_path": weights})):
+        with T.Context(device=0, **base, **kw) as c:
+            t0 = time.perf_counter()
+            tws, _, status, st, per = c.solve_batch(graphs, graph_stats=True)
+            dt = time.perf_counter() - t0
+        res[name] = (tws, status, per)
+        o = _outcomes(graphs, tws, status, per)
+        o["seconds"] = round(dt, 2)
+        o["graphs_solved_per_s"] = round(o["solved"] / dt, 2)
+        o["expansions"] = st["expansions"]
+        o["bounds_tried"] = st["decisions"]
+        out[name] = o
+        print(json.dumps({"leg": label, "policy": name, "seconds": round(dt, 1), "solved": o["solved"]}),
+              flush=True)
+    tp, sp, _ = res["plain"]
+    tl, sl, _ = res["learned"]
+    both = [t for t in range(len(graphs)) if sp[t] == 0 and sl[t] == 0]
+    if any(tp[t] != tl[t] for t in both):
+        raise RuntimeError(f"{label}: the learned start bound changed an answer")
+    out["identical_on_both_solved"] = len(both)
+    out["learned_speedup"] = round(out["learned"]["graphs_solved_per_s"] / out["plain"]["graphs_solved_per_s"], 3)
+    if ceiling:
+        kw = dict(base)
+        kw.pop("max_states", None)
+        exp = 0
+        with T.Context(device=0, max_states=max_states, **{k: v for k, v in kw.items()
+                                                           if k in ("reductions", "load_factor", "probe")}) as c:
+            t0 = time.perf_counter()
+            for t in both:
+                lb = T.mmw(graphs[t])
+                if reductions:
+                    lb = max(lb, len(T.reductions(graphs[t])[0]) - 1)
+                for k in ([int(tp[t])] + ([int(tp[t]) - 1] if tp[t] > lb else [])):
+                    _, st = c.decide(graphs[t], k)
+                    exp += st["expansions"]
+            dt = time.perf_counter() - t0
+        out["ceiling"] = {"graphs": len(both), "seconds": round(dt, 2), "graphs_per_s": round(len(both) / dt, 2),
+                          "expansions": exp,
+                          "note": "decide(tw) and decide(tw-1) one graph at a time on the single-graph path"}
+    return out
+
+
+def large_leg(cap_log2: int = 29) -> dict:
+    """The large single instance: random partial 12-tree on 64 vertices, 80%
+    of edges kept (seed 4001), decide(12) (its minor-min-width bound, so the
+    bound that certifies tw = 12), exact table against the Bloom variant of
+    §3.2, each level capped at 2^cap_log2 states: the levels up to the cap,
+    their expansion kernel time and rate.  The full search outgrows one GPU's
+    288 GB; the cap stops it with TW_ECAPACITY and the levels before it are
+    reported."""
+    from paper_1709_09990_amd import graphs as G
+    from paper_1709_09990_amd import tw as T
+    rows = G.workload_large_n64()
+    out = {"graph": "partial 12-tree, n=64, 80% edges kept, seed 4001", "k": 12,
+           "max_states_per_level": 1 << cap_log2}
+    for name, dedup in (("exact", T.TW_DEDUP_EXACT), ("bloom", T.TW_DEDUP_BLOOM)):
+        with T.Context(device=0, timing=True, dedup=dedup, max_states=1 << cap_log2) as c:
+            st = {}
+            t0 = time.perf_counter()
+            status = "YES/NO"
+            try:
+                yes, st = c.decide(rows, 12, stats_on_error=st)
+                status = "YES" if yes else "NO"
+            except T.TwError as e:
+                status = f"stopped: status {e.status}"
+            dt = time.perf_counter() - t0
+        ks = st.get("kernel_seconds", 0.0)
+        out[name] = {"outcome": status, "seconds": round(dt, 2), "levels": st.get("levels"),
+                     "peak_level": st.get("peak_frontier"), "expansions": st.get("expansions"),
+                     "kernel_seconds": round(ks, 3),
+                     "kernel_expansions_per_s": st.get("expansions", 0) / ks if ks else None}
+        print(json.dumps({"leg": "large_n64", name: out[name]}), flush=True)
+    return out
+
+
 def reductions_leg(graphs: dict, steps: int = 2) -> dict:
     """The same single-graph solves with the clique skip and disjoint-path
     edges of §3.1 (TW_REDUCE_CLIQUE_PATHS): time per step and work, answers
@@ -268,6 +455,14 @@ def main():
     ap.add_argument("--no-probe", action="store_true", help="skip the random-access reference measurement")
     ap.add_argument("--no-reduce", action="store_true", help="skip the single-graph leg with the section 3.1 reductions")
     ap.add_argument("--mmw", action="store_true", help="add a single-graph leg with per-state minor-min-width pruning")
+    ap.add_argument("--no-small", action="store_true", help="skip the G(20, 0.3) captured-loop leg")
+    ap.add_argument("--batch-n16-48", action="store_true",
+                    help="add the 512-graph batch with n 16..48 (seeds 3000+), plain vs learned, per-level cap")
+    ap.add_argument("--learned-n20-56", action="store_true",
+                    help="add the 2,048 held-out graphs with n 20..56 (seeds 600000+), plain vs learned vs ceiling")
+    ap.add_argument("--cap", type=int, default=1 << 26, help="states per level for the two legs above")
+    ap.add_argument("--reduce-batches", action="store_true", help="run the two legs above with the section 3.1 reductions")
+    ap.add_argument("--large-n64", action="store_true", help="add the n=64 partial 12-tree leg (exact vs Bloom, capped levels)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -375,8 +570,22 @@ def main():
         m["slowdown_vs_plain_step"] = round(m["ms_per_step"] / out["ms_per_step"], 3)
         m["states_expanded_plain_per_step"] = total["states_expanded"] // args.steps
         out["mmw_prune"] = m
+    if not args.no_small:
+        out["small_graphs"] = config1_leg()
     if not args.no_batch:
         out["batch"] = batch_leg()
+    if args.large_n64:
+        out["large_n64"] = large_leg()
+    if args.batch_n16_48 or args.learned_n20_56:
+        from paper_1709_09990_amd import graphs as G
+        wts = WEIGHTS_N40_REDUCED if args.reduce_batches else WEIGHTS
+        if args.batch_n16_48:
+            out["batch_n16_48"] = batch_config_leg(G.workload_batch(512, seed0=3000, n_lo=16, n_hi=48),
+                                                   "batch_n16_48", args.cap, wts, args.reduce_batches)
+        if args.learned_n20_56:
+            out["learned_n20_56"] = batch_config_leg(G.workload_batch(2048, seed0=600000, n_lo=20, n_hi=56),
+                                                     "learned_n20_56", args.cap, wts, args.reduce_batches,
+                                                     ceiling=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -123,7 +123,32 @@ typedef struct {
                                  trace sink are the unpruned ones; the kept-state counts go to
                                  tw_stats.states_expanded).  tw_solve_batch then solves every graph on the
                                  tw_solve path. */
+    /* Device memory from the caller (it owns it; a torch tensor, say):
+       when workspace is non-NULL, every device buffer of the context (levels, hash tables, counters,
+       batch arenas) is carved from [workspace, workspace + workspace_bytes) and the library calls
+       no hipMalloc for them; a level that does not fit fails with TW_ENOMEM.  The range must stay
+       valid and unused by the caller until tw_ctx_destroy.  tw_solve_batch then solves the graphs
+       bound for the single-graph path on this context, after the batched ones.  The learned start
+       bound's network (TW_K_LEARNED) keeps its own small allocation. */
+    void *workspace;
+    size_t workspace_bytes;
+    int fault_inject_level;   /* test hook (0 = off): the first build of level i = fault_inject_level of
+                                 every bound is treated as an overflow, so the regrow -> replay path
+                                 runs (tw_stats.retries counts it) and the level is built again; in
+                                 the batched search the graph reaching that level leaves the batch
+                                 for the single-graph path.  Answers and levels are unchanged; with
+                                 max_states at that level's size the replay fails with TW_ECAPACITY */
+    int capture;              /* TW_CAPTURE_AUTO (default): tw_solve (and tw_solve_batch's single-graph
+                                 path) runs a bound's whole level loop (Listing 1, §3.1) as one replay of
+                                 a HIP graph when every level fits its binomial bound C(m, i) within
+                                 256 MiB (n <= 25 or so; exact dedup, no MMW pruning, no test hooks): the
+                                 launches read each level's size and the bound from device memory and do
+                                 nothing past an empty level, so the host waits once per bound instead of
+                                 once per level.  The graph is captured once per graph shape and kept by
+                                 the context.  TW_CAPTURE_OFF: the host-driven level loop always */
 } tw_options;
+
+enum { TW_CAPTURE_AUTO = 0, TW_CAPTURE_OFF = 1 };
 
 enum { TW_REDUCE_NONE = 0, TW_REDUCE_CLIQUE_PATHS = 1 };
 enum { TW_BATCH_ROUNDS = 0, TW_BATCH_PERSISTENT = 1 };
@@ -151,7 +176,9 @@ tw_status tw_ctx_create(const tw_options *options, tw_ctx **out);
 void tw_ctx_destroy(tw_ctx *ctx);
 
 /* decide(k) of Listing 1 (§3.1): *out_yes = 1 iff tw(G) <= k.  k >= n-1 is
- * YES without a level.  stats may be NULL. */
+ * YES without a level.  stats may be NULL; it receives the counters of the
+ * levels built also when the call fails (TW_ECAPACITY or TW_ENOMEM at some
+ * level: the counters of the levels before it). */
 tw_status tw_decide(tw_ctx *ctx, const tw_graph *g, int32_t k, int32_t *out_yes, tw_stats *stats);
 
 /* tw(G) and an elimination order of that width (§2): ascending k from the
@@ -193,11 +220,42 @@ typedef struct {
     uint32_t decisions;       /* bounds tried */
     int32_t path;             /* 0: batched on the device, 1: single-graph path, 2: trivial (tw = n-1) */
     int32_t reserved;
+    uint64_t peak_any;        /* largest level met over the graph's search; for a graph that failed with
+                                 TW_ECAPACITY, at least max_states (the size the failing level reached) */
 } tw_graph_stats;
 
 tw_status tw_solve_batch(tw_ctx *ctx, const tw_graph *gs, uint32_t count, int32_t *out_tw,
                          int32_t *out_orders, tw_status *out_status, tw_graph_stats *out_graph_stats,
                          tw_stats *stats);
+
+/* Test hook for the batched search: one record per level a graph's batched
+ * search built (Listing 1's level loop, §3.1, run for many graphs at once),
+ * in the order built.  digest_sum is the sum mod 2^64 of the splitmix64
+ * output function (Steele, Lea and Flood) over the level's states, digest_xor
+ * the xor of MurmurHash3's fmix64 over them: equal sets give equal digests
+ * whatever order the states were found in. */
+typedef struct {
+    int32_t k;
+    int32_t level;        /* i >= 1: the record describes level i of bound k */
+    uint64_t count;       /* |level i| */
+    uint64_t successors;  /* feasible (S, v) pairs from level i-1 (duplicates included) */
+    uint64_t digest_sum;
+    uint64_t digest_xor;
+} tw_batch_level;
+
+/* tw_solve_batch with every batched graph's levels recorded.  Up to
+ * max_records records per graph go to out_records[t * max_records ...];
+ * out_nrecords[t] is the number the graph's successful batched attempt made
+ * (above max_records: only the first max_records were kept), 0 for graphs
+ * solved on the single-graph path or trivially.  first_arena_states (0: as
+ * tw_solve_batch) sets the arena of the first batched attempt; graphs that
+ * outgrow it get the retry with four times the arena (level rounds), whose
+ * records replace the first attempt's.  Other arguments and outcomes as
+ * tw_solve_batch.  TW_EINVAL if max_records is 0 or an output is NULL. */
+tw_status tw_trace_batch(tw_ctx *ctx, const tw_graph *gs, uint32_t count, uint64_t first_arena_states,
+                         uint32_t max_records, tw_batch_level *out_records, uint32_t *out_nrecords,
+                         int32_t *out_tw, int32_t *out_orders, tw_status *out_status,
+                         tw_graph_stats *out_graph_stats);
 
 /* One level of a bound-k search, as handed to a trace sink. */
 typedef struct {
@@ -215,6 +273,36 @@ typedef struct {
 tw_status tw_trace_decide(tw_ctx *ctx, const tw_graph *g, int32_t k,
                           void (*sink)(const tw_level_record *rec, void *user), void *user,
                           int32_t *out_yes);
+
+/* ---------------------------------------------------------------------------
+ * Graphs of up to 126 vertices.  The paper keeps states as bitsets and notes
+ * that wider bitsets extend the method (§3.1, §4.2); here a state is two
+ * 64-bit words (vertices 0..63, then 64..125).  The limit of 126 comes from
+ * the exact table: gfx950's widest compare-and-swap is 64 bits, so a slot
+ * holds the state as two 63-bit halves, each word keeping one bit to tell a
+ * free or unpublished half from a written one.  Same search as tw_decide /
+ * tw_solve with exact duplicate removal (options.dedup, reductions, mmw_prune
+ * and partition do not apply; the learned start bound is not used).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t n;          /* 1 <= n <= 126 */
+    const uint64_t *adj; /* 2n words: row i is adj[2i] (vertices 0..63) and adj[2i+1] (64..125);
+                            symmetric, no self-loops, no bits at positions >= n; caller-owned */
+} tw_graph128;
+
+/* decide(k) of Listing 1 (§3.1) on a graph of up to 126 vertices. */
+tw_status tw_decide128(tw_ctx *ctx, const tw_graph128 *g, int32_t k, int32_t *out_yes, tw_stats *stats);
+/* tw(G) and an order of that width (out_order: n entries), ascending bounds
+ * from the minor-min-width bound; after the first YES the order is rebuilt
+ * from the search restricted to the subsets of one last-level state. */
+tw_status tw_solve128(tw_ctx *ctx, const tw_graph128 *g, int32_t *out_tw, int32_t *out_order, tw_stats *stats);
+/* Test hook as tw_trace_decide; each record's states array holds 2 words per
+ * state (low, high), count states. */
+tw_status tw_trace_decide128(tw_ctx *ctx, const tw_graph128 *g, int32_t k,
+                             void (*sink)(const tw_level_record *rec, void *user), void *user, int32_t *out_yes);
+/* Host only: tw_mmw and tw_order_width for graphs of up to 126 vertices. */
+tw_status tw_mmw128(const tw_graph128 *g, int32_t *out_lb);
+tw_status tw_order_width128(const tw_graph128 *g, const int32_t *order, int32_t *out_width);
 
 /* Minor-min-width lower bound with the second-smallest-degree improvement
  * (§3.3): each round takes the lowest-index vertex of minimum degree, deletes
@@ -280,6 +368,22 @@ tw_status tw_mpnn_predict(tw_mpnn *m, const tw_graph *gs, uint32_t count, float 
  * gradients are summed in graph order (deterministic). */
 tw_status tw_mpnn_gradients(tw_mpnn *m, const tw_graph *gs, uint32_t count, const float *targets,
                             float *out_loss, float *out_grads);
+/* Test hook: one graph's forward and backward pass (loss: the mean of the two
+ * outputs' squared errors against target[2]) with the float32 values of the
+ * kernels recorded before each bfloat16 rounding, so every product can be
+ * checked on its own against the same bfloat16 operands.  out_trace holds
+ * tw_mpnn_trace_floats() floats, each 64 x 64 block row-major [node][feature]:
+ *   [0, 3*4096)        A H_l, l = 0..2
+ *   [3*4096, 6*4096)   H_l Ws_l^T + (A H_l) Wn_l^T + b_l before the ReLU, l = 0..2
+ *   then 256 floats    r[128] (sum and max readout), y[2]
+ *   then 4096          dL/dH_3
+ *   then 3*4096        dL/dZ_l, l = 0..2
+ *   then 2*4096        dL/dZ_l Wn_l, l = 1, 2
+ *   then 2*4096        dL/dH_l, l = 1, 2
+ * out_grads (tw_mpnn_param_count() floats): the gradient of that loss. */
+uint32_t tw_mpnn_trace_floats(void);
+tw_status tw_mpnn_trace(tw_mpnn *m, const tw_graph *g, const float *target, float *out_trace, float *out_grads);
+
 /* One AdamW step (beta 0.9 / 0.999, eps 1e-8; weight decay on the matrices
  * only) on the loss above; *out_loss (nullable) is the loss before the step. */
 tw_status tw_mpnn_train_step(tw_mpnn *m, const tw_graph *gs, uint32_t count, const float *targets, float lr,
@@ -291,7 +395,8 @@ tw_status tw_mpnn_train_step(tw_mpnn *m, const tw_graph *gs, uint32_t count, con
  * 256-thread workgroups per compute unit like the expansion kernel.  mode 0:
  * one 16-byte load per operation, one in flight per lane (the probe of the
  * exact table); 1: one 64-bit compare-and-swap; 2: 16-byte loads, eight in
- * flight per lane.  *out_seconds is the kernel time (HIP events) scaled to
+ * flight per lane; 3: as 0 with the nontemporal hint; 4: one 8-byte load;
+ * 5: one 8-byte relaxed atomic load at system scope.  *out_seconds is the kernel time (HIP events) scaled to
  * exactly `count` operations.  TW_EINVAL on a bad argument, TW_ENOMEM if the
  * buffer does not fit, TW_EDEVICE on a HIP error. */
 tw_status tw_probe_rate(int device, uint64_t bytes, uint64_t count, int mode, double *out_seconds);

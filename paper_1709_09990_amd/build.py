@@ -15,7 +15,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtw.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["tw_kernels.hip", "tw_batch.hip", "tw_mpnn.hip", "tw_probe.hip", "tw_mmw.hip", "tw_runtime.cpp", "tw_mpnn_host.cpp"]
+SOURCES = ["tw_kernels.hip", "tw_wide.hip", "tw_batch.hip", "tw_mpnn.hip", "tw_probe.hip", "tw_mmw.hip",
+           "tw_runtime.cpp", "tw_mpnn_host.cpp"]
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -18,6 +18,19 @@ enum : uint32_t {
 constexpr int kBatchKeyBits = 48;   // keys below bit 48, table tag above
 constexpr int kBatchMaxN = 48;
 
+// One level of one graph's batched search, recorded in trace mode (a test
+// hook): the level's size, the feasible pairs that built it, and two
+// order-independent digests of its states (sum of the splitmix64 output
+// function, xor of MurmurHash3's fmix64).  Layout shared with tw_batch_level.
+struct BatchTraceRec {
+    int32_t k;
+    int32_t level;
+    uint64_t count;
+    uint64_t successors;
+    uint64_t digest_sum;
+    uint64_t digest_xor;
+};
+
 // Per-graph state, device resident.  Written by the host before the launch;
 // afterwards only by the wave that finishes a level of this graph (counters
 // by atomics).
@@ -49,6 +62,15 @@ struct BatchGraph {
     int32_t order[64];       // elimination order of the best YES run (width best_yes)
     uint64_t allowed;        // vertices that may be added to a state (all, or all but a maximum clique)
     const uint8_t *paths;    // 64 x 64 disjoint-path counts: bound k adds uv when > k (null: none)
+    // trace mode (null trace: off): one record per level built, up to trace_cap
+    BatchTraceRec *trace;
+    uint32_t trace_cap;
+    uint32_t trace_len;      // records written, or wanted when above trace_cap
+    unsigned long long digest_sum;  // digests of the level being built
+    unsigned long long digest_xor;
+    unsigned long long succ_mark;   // successors when the level being built started
+    int32_t fault_level;     // test hook: building this level counts as an overflow (0: off)
+    int32_t pad_;
 };
 
 // One level of one graph: nchunks tasks of up to chunk states.

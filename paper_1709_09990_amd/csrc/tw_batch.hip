@@ -39,6 +39,22 @@ __device__ __forceinline__ T ld_relaxed(T *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Digests of trace mode: two published 64-bit mixers, summed and xored over a
+// level's states so the result does not depend on the order states are won.
+__device__ __forceinline__ uint64_t splitmix64_out(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t fmix64(uint64_t z)
+{
+    z = (z ^ (z >> 33)) * 0xFF51AFD7ED558CCDull;
+    z = (z ^ (z >> 33)) * 0xC4CEB9FE1A85EC53ull;
+    return z ^ (z >> 33);
+}
+
 // Called by one lane: append a job for (g, level).
 __device__ void push_job(const BatchArgs &a, int g, int level, uint64_t begin, uint64_t count)
 {
@@ -133,6 +149,23 @@ __device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_c
     const int n = G->n;
     const int k = G->k;
     if (lane == 0) {
+        if (G->trace) {
+            // record level+1 of bound k, then start the next level's digests
+            // (before any job of this graph is published below)
+            if (G->trace_len < G->trace_cap) {
+                BatchTraceRec *r = &G->trace[G->trace_len];
+                r->k = k;
+                r->level = level + 1;
+                r->count = cnt;
+                r->successors = G->successors - G->succ_mark;
+                r->digest_sum = G->digest_sum;
+                r->digest_xor = G->digest_xor;
+            }
+            G->trace_len++;
+            G->digest_sum = 0;
+            G->digest_xor = 0;
+            G->succ_mark = G->successors;
+        }
         G->states += in_count;
         G->expansions += in_count * (uint64_t)(n - level);
         G->levels_run++;
@@ -142,7 +175,7 @@ __device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_c
         if (cnt > G->peak_k)
             G->peak_k = cnt;
     }
-    if (ovf || G->tag >= 0xFFFEu) {
+    if (ovf || G->tag >= 0xFFFEu || level + 1 == G->fault_level) {
         graph_done(a, G, kBatchFallback, lane);
         return;
     }
@@ -218,6 +251,7 @@ __device__ void process_chunk(const BatchArgs &a, int g, int level, uint64_t beg
     }
     const bool lane_allowed = ((G->allowed >> lane) & 1ull) != 0ull;
     const uint64_t lanebit = 1ull << lane;
+    const bool tracing = G->trace != nullptr;
 
     uint32_t staged = 0;
     uint64_t feasible = 0;
@@ -282,6 +316,10 @@ __device__ void process_chunk(const BatchArgs &a, int g, int level, uint64_t beg
                     }
                     cur = prev;
                 }
+            }
+            if (tracing && won) {
+                atomicAdd(&G->digest_sum, (unsigned long long)splitmix64_out(key));
+                atomicXor(&G->digest_xor, (unsigned long long)fmix64(key));
             }
             overflow = ballot(overflow) != 0ull;
             const uint64_t winners = ballot(won);

@@ -59,6 +59,30 @@ struct GatherArgs {
     uint64_t slice;                  // table slots per partition
 };
 
+// Gated level loop (one bound as a fixed launch sequence, for HIP graphs).
+struct CaptureCtl {
+    int k;                  // the bound
+    int L;                  // levels run: max(0, n - k - 1)
+    uint64_t allowed;       // vertices that may be added to a state
+};
+
+struct GateArgs {
+    const CaptureCtl *ctl;
+    LevelCounters *ctr;     // ctr[i]: the launch that builds level i+1 from level i
+    int level;              // i
+};
+
+struct BacktrackArgs {
+    const void *keys;       // every level, level i at keys + off[i] (key_bytes each)
+    const uint8_t *lastv;   // creating vertex, same offsets
+    const uint64_t *off;    // device: level offsets
+    const CaptureCtl *ctl;
+    const LevelCounters *ctr;
+    int32_t *order;         // out: order[0..L)
+    uint64_t *last_state;   // out: the level-L state the order ends in
+    int32_t *err;           // out: 1 if a predecessor was not found
+};
+
 constexpr int kMaxParts = 64;
 constexpr int kSubRegions = 64;
 constexpr int kEntryVShift = 58;     // entries carry v above bit 58 (n <= 58)
@@ -77,5 +101,13 @@ hipError_t launch_gather(const LevelArgs &a, const GatherArgs &ga, unsigned grid
 hipError_t launch_find(const void *keys, uint64_t count, uint64_t target, int key_bytes,
                        unsigned long long *result, hipStream_t s);
 hipError_t launch_zero_counters(LevelCounters *c, hipStream_t s);
+// Graphs of up to 126 vertices: keys are (low word, high word) pairs, a.adj
+// holds two words per row, a.allowed the low half of the allowed vertices.
+hipError_t launch_expand_wide(const LevelArgs &a, uint64_t allowed_hi, unsigned grid_blocks, hipStream_t s);
+hipError_t launch_find_wide(const void *keys, uint64_t count, uint64_t lo, uint64_t hi, unsigned long long *result,
+                            hipStream_t s);
+hipError_t launch_prep_gated(const GateArgs &g, void *table, uint64_t bytes, hipStream_t s);
+hipError_t launch_expand_gated(const LevelArgs &a, const GateArgs &g, unsigned grid_blocks, hipStream_t s);
+hipError_t launch_backtrack(const BacktrackArgs &b, int key_bytes, hipStream_t s);
 
 }  // namespace twk

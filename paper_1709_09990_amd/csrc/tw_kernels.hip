@@ -163,7 +163,7 @@ __device__ __forceinline__ bool table_insert(const LevelArgs &a, K *table, K key
 // 64 lanes at once, so the probes of a wave run at full width and one memory
 // round trip serves 64 successors rather than the few of one state.
 template <typename K, bool kBloom>
-__global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
+__device__ __forceinline__ void expand_level(const LevelArgs &a)
 {
     constexpr uint32_t kQueue = 128;  // ring of pending successors per wave
     __shared__ K stage_key[kWavesPerBlock][kStage];
@@ -278,6 +278,107 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
     flush();
     if (lane == 0 && feasible)
         atomicAdd(&a.ctr->successors, (unsigned long long)feasible);
+}
+
+template <typename K, bool kBloom>
+__global__ __launch_bounds__(kBlock) void expand_kernel(LevelArgs a)
+{
+    expand_level<K, kBloom>(a);
+}
+
+// ---------------------------------------------------------------------------
+// Level loop of one bound as a fixed sequence of launches (captured once in a
+// HIP graph and replayed for every bound and graph of the same shape): level
+// i reads its size from the counters the launch for level i-1 left in device
+// memory, and its bound from the control block, and does nothing when it lies
+// beyond L(k), follows an empty level, or follows an overflow.
+// ---------------------------------------------------------------------------
+
+// Size of level `level`, or 0 when the level is not run for this bound.
+__device__ __forceinline__ uint64_t gated_count(const GateArgs &g)
+{
+    if (g.level >= g.ctl->L)
+        return 0;
+    if (g.level == 0)
+        return 1;
+    const LevelCounters &prev = g.ctr[g.level - 1];
+    return prev.overflow ? 0 : prev.out_count;
+}
+
+// Clears level `level`'s counters, and its table when the level runs.
+__global__ void prep_gated_kernel(GateArgs g, uint4 *table, uint64_t n16)
+{
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid == 0) {
+        LevelCounters *c = &g.ctr[g.level];
+        c->out_count = 0;
+        c->successors = 0;
+        c->overflow = 0;
+        c->pad = 0;
+    }
+    if (gated_count(g) == 0)
+        return;
+    const uint4 v = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (uint64_t i = gid; i < n16; i += (uint64_t)gridDim.x * blockDim.x)
+        table[i] = v;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void expand_gated_kernel(LevelArgs a, GateArgs g)
+{
+    const uint64_t cnt = gated_count(g);
+    if (cnt == 0)
+        return;
+    a.in_count = cnt;
+    a.k = g.ctl->k;
+    a.allowed = g.ctl->allowed;
+    expand_level<K, false>(a);
+}
+
+// One workgroup: the order of a YES run of the gated loop.  From the first
+// state of level L, each step reads the vertex that created the state, takes
+// it out, and finds the remaining set in the level below (every thread scans
+// a strided share; the lowest index found wins).  Writes order[0..L) and the
+// last state; *err = 1 if a predecessor is missing.
+template <typename K>
+__global__ __launch_bounds__(1024) void backtrack_kernel(BacktrackArgs b)
+{
+    __shared__ unsigned long long found;
+    const K *keys = (const K *)b.keys;
+    const int L = b.ctl->L;
+    if (L <= 0) {
+        if (threadIdx.x == 0)
+            *b.last_state = 0;
+        return;
+    }
+    uint64_t idx = 0;
+    uint64_t S = (uint64_t)keys[b.off[L]];
+    if (threadIdx.x == 0)
+        *b.last_state = S;
+    for (int i = L; i >= 1; --i) {
+        const int v = b.lastv[b.off[i] + idx];
+        if (threadIdx.x == 0)
+            b.order[i - 1] = v;
+        S &= ~(1ull << v);
+        if (i == 1)
+            break;
+        const uint64_t cnt = i - 1 == 0 ? 1 : b.ctr[i - 2].out_count;
+        if (threadIdx.x == 0)
+            found = ~0ull;
+        __syncthreads();
+        const K *lv = keys + b.off[i - 1];
+        for (uint64_t t = threadIdx.x; t < cnt; t += blockDim.x)
+            if ((uint64_t)lv[t] == S)
+                atomicMin(&found, (unsigned long long)t);
+        __syncthreads();
+        idx = found;
+        __syncthreads();
+        if (idx == ~0ull) {
+            if (threadIdx.x == 0)
+                *b.err = 1;
+            return;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -573,6 +674,32 @@ hipError_t launch_expand(const LevelArgs &a, unsigned grid_blocks, hipStream_t s
         else
             hipLaunchKernelGGL((expand_kernel<uint64_t, false>), dim3(grid_blocks), dim3(kBlock), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_gated(const GateArgs &g, void *table, uint64_t bytes, hipStream_t s)
+{
+    const uint64_t n16 = bytes / 16;
+    hipLaunchKernelGGL(prep_gated_kernel, dim3(blocks_for(n16 ? n16 : 1, 256, 8192)), dim3(256), 0, s, g,
+                       (uint4 *)table, n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_gated(const LevelArgs &a, const GateArgs &g, unsigned grid_blocks, hipStream_t s)
+{
+    if (a.key_bytes == 4)
+        hipLaunchKernelGGL(expand_gated_kernel<uint32_t>, dim3(grid_blocks), dim3(kBlock), 0, s, a, g);
+    else
+        hipLaunchKernelGGL(expand_gated_kernel<uint64_t>, dim3(grid_blocks), dim3(kBlock), 0, s, a, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_backtrack(const BacktrackArgs &b, int key_bytes, hipStream_t s)
+{
+    if (key_bytes == 4)
+        hipLaunchKernelGGL(backtrack_kernel<uint32_t>, dim3(1), dim3(1024), 0, s, b);
+    else
+        hipLaunchKernelGGL(backtrack_kernel<uint64_t>, dim3(1), dim3(1024), 0, s, b);
     return hipGetLastError();
 }
 

@@ -22,7 +22,25 @@ struct MpnnArgs {
     float *pred;             // [graphs][2] or nullptr
     float *sq_err;           // [graphs][2] or nullptr
     float *grads;            // [graphs][MpnnParams] per-graph gradients, or nullptr (inference)
+    float *trace;            // [graphs][MpnnTraceFloats] float32 intermediates (test hook), or nullptr
 };
+
+// Trace layout (floats, per graph; every 64 x 64 block row-major [node][feature]):
+//   M_l  = A H_l before its bfloat16 rounding       l = 0..2   at MpnnTrM + l * 4096
+//   Z_l  = H_l Ws^T + M_l Wn^T + b before the ReLU  l = 0..2   at MpnnTrZ + l * 4096
+//   r [128], y [2]                                             at MpnnTrR
+//   dH_3 (gradient of the loss with respect to H_3)            at MpnnTrDH3
+//   dZ_l before its bfloat16 rounding               l = 0..2   at MpnnTrDZ + l * 4096
+//   P_l = dZ_l Wn_l before its bfloat16 rounding    l = 1, 2   at MpnnTrP + (l - 1) * 4096
+//   dH_l = dZ_l Ws_l + A P_l                        l = 1, 2   at MpnnTrDH + (l - 1) * 4096
+constexpr int MpnnTrM = 0;
+constexpr int MpnnTrZ = 3 * 4096;
+constexpr int MpnnTrR = 6 * 4096;
+constexpr int MpnnTrDH3 = MpnnTrR + 256;
+constexpr int MpnnTrDZ = MpnnTrDH3 + 4096;
+constexpr int MpnnTrP = MpnnTrDZ + 3 * 4096;
+constexpr int MpnnTrDH = MpnnTrP + 2 * 4096;
+constexpr int MpnnTraceFloats = MpnnTrDH + 2 * 4096;
 
 struct MpnnOptArgs {
     float *params, *m, *v;

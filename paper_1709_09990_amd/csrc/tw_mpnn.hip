@@ -99,6 +99,7 @@ __global__ __launch_bounds__(256) void mpnn_kernel(MpnnArgs a)
     const int n = a.n[g];
     const uint64_t *rows = a.adj + (size_t)g * 64;
     const float *x = a.feat + (size_t)g * NP * MpnnFeat;
+    float *tr = a.trace ? a.trace + (size_t)g * MpnnTraceFloats : nullptr;
 
     // adjacency, mask, H0 (node- and feature-major)
     for (int e = tid; e < NP * NP; e += 256) {
@@ -124,6 +125,8 @@ __global__ __launch_bounds__(256) void mpnn_kernel(MpnnArgs a)
             const uint16_t b = to_bf16(acc[e]);
             s.mn[v * LD + f] = b;
             s.mf[l][f * LD + v] = b;
+            if (tr)
+                tr[MpnnTrM + l * 4096 + v * 64 + f] = acc[e];
         }
         __syncthreads();
         // Z = H_l Ws^T + M Wn^T + b  (K = features; B operands = weights [out][in])
@@ -137,6 +140,8 @@ __global__ __launch_bounds__(256) void mpnn_kernel(MpnnArgs a)
         for (int e = 0; e < 16; ++e) {
             const int v = rq + acc_row(e, lane), o = cq + acc_col(lane);
             float z = acc[e] + bias[o];
+            if (tr)
+                tr[MpnnTrZ + l * 4096 + v * 64 + o] = z;
             z = z > 0.f ? z : 0.f;
             z *= s.mask[v];
             const uint16_t b = to_bf16(z);
@@ -169,6 +174,8 @@ __global__ __launch_bounds__(256) void mpnn_kernel(MpnnArgs a)
         s.amax[j] = arg;
     }
     __syncthreads();
+    if (tr && tid < 2 * HD)
+        tr[MpnnTrR + tid] = s.r[tid];
     const float *Wo = a.params + 3 * MpnnLayerParams;
     const float *bo = Wo + 2 * 2 * HD;
     if (tid < 2) {
@@ -176,6 +183,8 @@ __global__ __launch_bounds__(256) void mpnn_kernel(MpnnArgs a)
         for (int j = 0; j < 2 * HD; ++j)
             y += Wo[tid * 2 * HD + j] * s.r[j];
         s.y[tid] = y;
+        if (tr)
+            tr[MpnnTrR + 2 * HD + tid] = y;
         if (a.pred)
             a.pred[(size_t)g * 2 + tid] = y;
         if (a.targets) {
@@ -206,6 +215,8 @@ __global__ __launch_bounds__(256) void mpnn_kernel(MpnnArgs a)
         if (v < n && s.amax[j] == v)
             d += s.dr[HD + j];
         s.f32[v * LDF + j] = d;
+        if (tr)
+            tr[MpnnTrDH3 + v * 64 + j] = d;
     }
     __syncthreads();
 
@@ -217,6 +228,8 @@ __global__ __launch_bounds__(256) void mpnn_kernel(MpnnArgs a)
             const bool on = from_bf16(s.hf[l + 1][o * LD + v]) > 0.f;
             const float dz = on ? s.f32[v * LDF + o] * s.mask[v] : 0.f;
             s.f32[v * LDF + o] = dz;
+            if (tr)
+                tr[MpnnTrDZ + l * 4096 + v * 64 + o] = dz;
             const uint16_t b = to_bf16(dz);
             s.dzn[v * LD + o] = b;
             s.dzf[o * LD + v] = b;
@@ -244,16 +257,22 @@ __global__ __launch_bounds__(256) void mpnn_kernel(MpnnArgs a)
         const uint16_t *WnT = a.wnbt + (size_t)l * HD * HD;
         acc = mma32(s.dzn + rq * LD, LD, WnT + cq * HD, HD, HD, zero16(), lane);
 #pragma unroll
-        for (int e = 0; e < 16; ++e)
+        for (int e = 0; e < 16; ++e) {
             s.pf[(cq + acc_col(lane)) * LD + rq + acc_row(e, lane)] = to_bf16(acc[e]);
+            if (tr)
+                tr[MpnnTrP + (l - 1) * 4096 + (rq + acc_row(e, lane)) * 64 + cq + acc_col(lane)] = acc[e];
+        }
         __syncthreads();
         // dH_l = dZ Ws + A P
         acc = mma32(s.dzn + rq * LD, LD, WsT + cq * HD, HD, HD, zero16(), lane);
         acc = mma32(s.adj + rq * LD, LD, s.pf + cq * LD, LD, NP, acc, lane);
         __syncthreads();  // f32 (dZ) fully consumed
 #pragma unroll
-        for (int e = 0; e < 16; ++e)
+        for (int e = 0; e < 16; ++e) {
             s.f32[(rq + acc_row(e, lane)) * LDF + cq + acc_col(lane)] = acc[e];
+            if (tr)
+                tr[MpnnTrDH + (l - 1) * 4096 + (rq + acc_row(e, lane)) * 64 + cq + acc_col(lane)] = acc[e];
+        }
         __syncthreads();
     }
 }

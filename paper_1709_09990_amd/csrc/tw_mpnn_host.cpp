@@ -327,6 +327,42 @@ tw_status tw_mpnn_gradients(tw_mpnn *m, const tw_graph *gs, uint32_t count, cons
     return TW_OK;
 }
 
+uint32_t tw_mpnn_trace_floats(void) { return (uint32_t)twk::MpnnTraceFloats; }
+
+tw_status tw_mpnn_trace(tw_mpnn *m, const tw_graph *g, const float *target, float *out_trace, float *out_grads)
+{
+    if (!m || !g || !target || !out_trace || !out_grads)
+        return TW_EINVAL;
+    (void)hipSetDevice(m->device);
+    tw_status s = upload_graphs(m, g, 1);
+    if (s != TW_OK)
+        return s;
+    float *dtr = nullptr;
+    if (dmalloc(&dtr, (size_t)twk::MpnnTraceFloats) != hipSuccess) {
+        (void)hipGetLastError();
+        return TW_ENOMEM;
+    }
+    twk::MpnnArgs a = base_args(m);
+    a.pred = m->pred;
+    a.trace = dtr;
+    a.grads = m->partial;
+    a.sq_err = m->sq;
+    a.grad_scale = 0.5f;  // one graph, two outputs: the loss is their mean
+    tw_status st = TW_OK;
+    if (hipMemcpyAsync(m->targets, target, 2 * 4, hipMemcpyHostToDevice, m->stream) != hipSuccess ||
+        (a.targets = m->targets, twk::launch_mpnn(a, 1, m->stream)) != hipSuccess ||
+        hipMemcpyAsync(out_trace, dtr, (size_t)twk::MpnnTraceFloats * 4, hipMemcpyDeviceToHost, m->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(out_grads, m->partial, (size_t)twk::MpnnParams * 4, hipMemcpyDeviceToHost, m->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(m->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        st = TW_EDEVICE;
+    }
+    (void)hipFree(dtr);
+    return st;
+}
+
 tw_status tw_mpnn_train_step(tw_mpnn *m, const tw_graph *gs, uint32_t count, const float *targets, float lr,
                              float weight_decay, float *out_loss)
 {

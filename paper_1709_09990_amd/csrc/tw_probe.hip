@@ -39,6 +39,17 @@ __global__ __launch_bounds__(kProbeBlock) void probe_rate_kernel(uint4 *buf, uin
             if (kMode == 0) {
                 const uint4 v = buf[b];
                 acc ^= v.x ^ v.w;
+            } else if (kMode == 3) {
+                using Vec = unsigned __attribute__((ext_vector_type(4)));
+                const Vec v = __builtin_nontemporal_load((const Vec *)&buf[b]);
+                acc ^= v.x ^ v.w;
+            } else if (kMode == 4) {
+                const uint64_t v = *(const uint64_t *)&buf[b];
+                acc ^= (uint32_t)v ^ (uint32_t)(v >> 32);
+            } else if (kMode == 5) {
+                const uint64_t v = __hip_atomic_load((const uint64_t *)&buf[b], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_SYSTEM);
+                acc ^= (uint32_t)v ^ (uint32_t)(v >> 32);
             } else {
                 unsigned long long *p = (unsigned long long *)&buf[b];
                 acc ^= (uint32_t)atomicCAS(p, ~0ull, (unsigned long long)(h | 1ull));
@@ -63,8 +74,17 @@ hipError_t launch_probe_rate(void *buf, uint64_t bytes, uint64_t per_thread, int
     else if (mode == 1)
         hipLaunchKernelGGL(probe_rate_kernel<1>, dim3(blocks), dim3(kProbeBlock), 0, s, (uint4 *)buf, n16,
                            per_thread, sink);
-    else
+    else if (mode == 2)
         hipLaunchKernelGGL(probe_rate_kernel<2>, dim3(blocks), dim3(kProbeBlock), 0, s, (uint4 *)buf, n16,
+                           per_thread, sink);
+    else if (mode == 3)
+        hipLaunchKernelGGL(probe_rate_kernel<3>, dim3(blocks), dim3(kProbeBlock), 0, s, (uint4 *)buf, n16,
+                           per_thread, sink);
+    else if (mode == 4)
+        hipLaunchKernelGGL(probe_rate_kernel<4>, dim3(blocks), dim3(kProbeBlock), 0, s, (uint4 *)buf, n16,
+                           per_thread, sink);
+    else
+        hipLaunchKernelGGL(probe_rate_kernel<5>, dim3(blocks), dim3(kProbeBlock), 0, s, (uint4 *)buf, n16,
                            per_thread, sink);
     return hipGetLastError();
 }

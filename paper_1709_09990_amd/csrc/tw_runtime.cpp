@@ -30,10 +30,73 @@ namespace {
 
 using twk::LevelCounters;
 
+// First-fit allocator over one caller-given device range (options.workspace):
+// host bookkeeping only, blocks of 256-byte multiples, neighbours merged on
+// release.
+struct Carver {
+    uintptr_t base = 0;
+    size_t bytes = 0;
+    std::vector<std::pair<size_t, size_t>> free_list;  // (offset, size), ascending, merged
+
+    static size_t round_up(size_t n) { return (n + 255) & ~(size_t)255; }
+    void reset(void *p, size_t n)
+    {
+        const uintptr_t b = ((uintptr_t)p + 255) & ~(uintptr_t)255;
+        const size_t lost = (size_t)(b - (uintptr_t)p);
+        base = b;
+        bytes = n > lost ? (n - lost) & ~(size_t)255 : 0;
+        free_list.clear();
+        if (bytes)
+            free_list.emplace_back(0, bytes);
+    }
+    void *take(size_t n)
+    {
+        n = round_up(n);
+        for (size_t t = 0; t < free_list.size(); ++t) {
+            if (free_list[t].second < n)
+                continue;
+            const size_t off = free_list[t].first;
+            free_list[t].first += n;
+            free_list[t].second -= n;
+            if (!free_list[t].second)
+                free_list.erase(free_list.begin() + (long)t);
+            return (void *)(base + off);
+        }
+        return nullptr;
+    }
+    void put(void *p, size_t n)
+    {
+        n = round_up(n);
+        const size_t off = (size_t)((uintptr_t)p - base);
+        size_t i = 0;
+        while (i < free_list.size() && free_list[i].first < off)
+            ++i;
+        free_list.insert(free_list.begin() + (long)i, std::make_pair(off, n));
+        if (i + 1 < free_list.size() && free_list[i].first + free_list[i].second == free_list[i + 1].first) {
+            free_list[i].second += free_list[i + 1].second;
+            free_list.erase(free_list.begin() + (long)i + 1);
+        }
+        if (i > 0 && free_list[i - 1].first + free_list[i - 1].second == free_list[i].first) {
+            free_list[i - 1].second += free_list[i].second;
+            free_list.erase(free_list.begin() + (long)i);
+        }
+    }
+    size_t largest() const
+    {
+        size_t m = 0;
+        for (const auto &f : free_list)
+            m = std::max(m, f.second);
+        return m;
+    }
+};
+
 struct Buf {
     void *p = nullptr;
     size_t bytes = 0;
+    Carver *from = nullptr;  // carved from a caller range (null: hipMalloc)
 };
+
+struct Captured;  // an instantiated level loop (below)
 
 struct Level {
     Buf keys;
@@ -57,6 +120,7 @@ struct tw_ctx {
     std::string err;
     std::vector<Buf> cache;  // free device buffers kept for reuse
     Buf d_adj, d_ctr, d_find;
+    Buf d_adj_wide;          // two words per row (graphs of up to 126 vertices)
     Buf table;               // current hash table (reused between levels)
     Buf bloom;               // Bloom bit array (Bloom variant only)
     Buf parts, part_meta;    // partitioned insert: successor buffer, counters and prefixes
@@ -64,6 +128,12 @@ struct tw_ctx {
     unsigned long long *h_find = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     tw_mpnn *net = nullptr;  // learned start bound (k_policy = TW_K_LEARNED)
+    Carver ws;               // options.workspace, when given
+    Carver *carve = nullptr; // where device buffers come from (null: hipMalloc)
+    uint64_t keep_budget = 1ull << 30;  // bytes of levels tw_solve keeps for the order
+    bool no_capture = false; // set while a call must not create graphs or pinned memory
+    std::vector<Captured *> captured;  // instantiated level loops, by graph shape
+    void *h_cap = nullptr;   // pinned host block for the captured loop's control and counters
 };
 
 namespace {
@@ -141,9 +211,23 @@ tw_status validate(tw_ctx *c, const tw_graph *g, Graph &out)
 
 void release(tw_ctx *c, Buf &b)
 {
-    if (b.p)
+    if (b.p && b.from)
+        b.from->put(b.p, b.bytes);
+    else if (b.p)
         c->cache.push_back(b);
     b = Buf{};
+}
+
+// Device bytes the next buffers may take: the largest free block of the
+// caller's range, else what the device reports free.
+size_t free_device_bytes(tw_ctx *c)
+{
+    if (c->carve)
+        return c->carve->largest();
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
+        free_b = (size_t)16 << 30;
+    return free_b;
 }
 
 void drop_cache(tw_ctx *c)
@@ -159,6 +243,16 @@ tw_status acquire(tw_ctx *c, Buf &b, size_t bytes)
         return TW_OK;
     release(c, b);
     bytes = std::max<size_t>(bytes, 256);
+    if (c->carve) {
+        void *p = c->carve->take(bytes);
+        if (!p)
+            return fail(c, TW_ENOMEM, "%zu bytes do not fit the caller's device range (largest free block %zu)",
+                        bytes, c->carve->largest());
+        b.p = p;
+        b.bytes = bytes;
+        b.from = c->carve;
+        return TW_OK;
+    }
     int best = -1;
     for (size_t t = 0; t < c->cache.size(); ++t)
         if (c->cache[t].bytes >= bytes &&
@@ -440,6 +534,7 @@ void add_run_stats(RunStats &into, const RunStats &from)
 
 struct GraphOutcome {
     uint64_t peak_yes = 0, expansions = 0, states = 0;
+    uint64_t peak_any = 0;  // largest level met (for a failed search: what the failing level reached)
     int32_t start_k = 0;
     uint32_t decisions = 0;
     int32_t path = 1;
@@ -548,9 +643,8 @@ tw_status prune_level(tw_ctx *c, Level &in, int n, int k, int kb, RunStats &rs)
 enum Keep {
     kKeepPair = 0,     // only the current pair; levels.back() is the last level reached
     kKeepAll = 1,      // levels[0..L] stay on the device, each trimmed to its exact size
-    kKeepIfSmall = 2,  // as kKeepAll while the kept levels fit kKeepBudget bytes, then as kKeepPair
+    kKeepIfSmall = 2,  // as kKeepAll while the kept levels fit keep_budget bytes, then as kKeepPair
 };
-constexpr uint64_t kKeepBudget = 1ull << 30;
 
 // Runs decide(k).  Levels are retained as `keep` says (levels.size() == L + 1
 // after a YES means every level was kept, for order reconstruction).  With
@@ -592,9 +686,7 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, int keep, const Sink *sin
     const float alpha = (c->opt.load_factor > 0.f && c->opt.load_factor <= 0.9f)
                             ? c->opt.load_factor
                             : 0.25f;
-    size_t dev_free = 0, dev_total = 0;
-    if (hipMemGetInfo(&dev_free, &dev_total) != hipSuccess)
-        dev_free = (size_t)16 << 30;
+    const size_t dev_free = free_device_bytes(c);
     double growth = (double)n;      // |level 1| <= n
     double pair_ratio = (double)n;  // feasible pairs per state of the previous level
     Buf scratch_keys, scratch_lastv;
@@ -634,6 +726,7 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, int keep, const Sink *sin
         uint64_t part_guess = 0;  // successor-buffer entries (partitioned insert)
 
         uint64_t out_count = 0, succ = 0;
+        bool injected = false;
         for (;;) {
             if (c->opt.max_states && guess > c->opt.max_states)
                 guess = std::max<uint64_t>(c->opt.max_states, 1);
@@ -799,7 +892,12 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, int keep, const Sink *sin
                 HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
                 rs.kernel_seconds += ms * 1e-3;
             }
-            const LevelCounters h = *c->h_ctr;
+            LevelCounters h = *c->h_ctr;
+            if (c->opt.fault_inject_level == i + 1 && !injected) {
+                // test hook: this level's first build counts as an overflow
+                injected = true;
+                h.overflow = 1;
+            }
             if (!h.overflow) {
                 out_count = h.out_count;
                 succ = h.successors;
@@ -808,11 +906,12 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, int keep, const Sink *sin
             // overflow: regrow and replay the level (h.out_count is a lower bound)
             rs.retries++;
             if (c->opt.max_states && out_cap >= c->opt.max_states) {
+                run_peak = std::max<uint64_t>(run_peak, h.out_count);
                 status = fail(c, TW_ECAPACITY, "level %d needs more than max_states=%llu states",
                               i + 1, (unsigned long long)c->opt.max_states);
                 goto done;
             }
-            if (!bloom && out_cap >= bound && (double)slots * 0.8 >= (double)bound) {
+            if (!bloom && !injected && out_cap >= bound && (double)slots * 0.8 >= (double)bound) {
                 status = fail(c, TW_EDEVICE, "overflow at level %d with capacity at its bound", i + 1);
                 goto done;
             }
@@ -831,7 +930,7 @@ tw_status run_decide(tw_ctx *c, const Graph &g, int k, int keep, const Sink *sin
 
         if (keep_levels && keep == kKeepIfSmall) {
             kept_bytes += out_count * (uint64_t)(kb + 1);
-            if (kept_bytes > kKeepBudget) {
+            if (kept_bytes > c->keep_budget) {
                 // too large to keep every level: continue with the current pair only
                 keep_levels = false;
                 for (size_t t = 0; t + 1 < levels.size(); ++t) {
@@ -1006,6 +1105,718 @@ tw_status decide_checked(tw_ctx *c, const Graph &g, const Reduction *red, int k,
     return s;
 }
 
+// ---------------------------------------------------------------------------
+// Captured level loop.  For graphs whose every level fits its binomial bound
+// in a modest budget, the level loop of a bound (Listing 1) is a fixed
+// sequence of launches — per level one clearing launch and one expansion —
+// whose sizes and bound come from device memory, captured once per graph
+// shape in a HIP graph and replayed for every bound (and every later graph of
+// that shape): one launch and one readback per bound instead of a launch
+// sequence and a host wait per level.  Level i has room for C(m, i) states (m
+// vertices may be added), which no exact level exceeds, so a replay cannot
+// overflow its capacity; a table overflow (probe backstop) sends the bound to
+// the host-driven loop.
+// ---------------------------------------------------------------------------
+struct Captured {
+    int n = 0, levels = 0;
+    std::vector<uint64_t> off;       // level offsets in states (levels + 1 entries)
+    Buf keys, lastv, table, ctr, ctl, off_dev, out;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+constexpr uint64_t kCaptureBudget = 256ull << 20;
+constexpr float kCaptureLoad = 0.25f;
+// internal status (beside the public 0..4): run this bound on the host-driven loop
+constexpr tw_status kNotCaptured = static_cast<tw_status>(7);
+
+struct CapHost {
+    twk::CaptureCtl ctl;
+    LevelCounters ctr[64];
+    int32_t order[64];
+    uint64_t last_state;
+    int32_t err;
+    int32_t pad2;
+};
+
+void destroy_captured(tw_ctx *c, Captured *cp)
+{
+    if (cp->exec)
+        (void)hipGraphExecDestroy(cp->exec);
+    if (cp->graph)
+        (void)hipGraphDestroy(cp->graph);
+    release(c, cp->keys);
+    release(c, cp->lastv);
+    release(c, cp->table);
+    release(c, cp->ctr);
+    release(c, cp->ctl);
+    release(c, cp->off_dev);
+    release(c, cp->out);
+    delete cp;
+}
+
+// The instantiated loop for graphs on n vertices, built on first use (the
+// context keeps the last kCaptureKeep); null when the path does not apply.
+// Level i has room for C(n, i) states: every level of any bound, with any set
+// of vertices allowed, fits.
+constexpr size_t kCaptureKeep = 4;
+
+Captured *capture_for(tw_ctx *c, const Graph &g)
+{
+    if (c->opt.capture == TW_CAPTURE_OFF || c->no_capture || !c->h_cap || c->opt.dedup != TW_DEDUP_EXACT ||
+        c->opt.mmw_prune != TW_MMW_NONE || c->opt.partition == 2 || c->opt.fault_inject_level ||
+        c->opt.capacity_override || g.n > 32 || g.n < 2)
+        return nullptr;
+    const int n = g.n;
+    for (Captured *cp : c->captured)
+        if (cp->n == n)
+            return cp->exec ? cp : nullptr;
+    const int levels = n - 1;  // bounds k >= 0 run at most n - 1 levels
+    std::vector<uint64_t> off((size_t)levels + 2, 0);
+    uint64_t widest = 1;
+    for (int i = 0; i <= levels; ++i) {
+        const uint64_t cap = std::max<uint64_t>(binom_sat(n, i), 1);
+        off[(size_t)i + 1] = off[(size_t)i] + cap;
+        widest = std::max(widest, cap);
+    }
+    const uint64_t states = off[(size_t)levels + 1];
+    const uint64_t slots_max = ((uint64_t)((double)widest / kCaptureLoad) + 64 + 63) / 64 * 64;
+    const uint64_t bytes = states * 5 + slots_max * 4;
+    if (bytes > kCaptureBudget || bytes > free_device_bytes(c) / 4)
+        return nullptr;
+    Captured *cp = new (std::nothrow) Captured();
+    if (!cp)
+        return nullptr;
+    cp->n = n;
+    cp->levels = levels;
+    cp->off = off;
+    if (c->captured.size() >= kCaptureKeep) {
+        (void)hipStreamSynchronize(c->stream);
+        destroy_captured(c, c->captured.front());
+        c->captured.erase(c->captured.begin());
+    }
+    c->captured.push_back(cp);  // cached even when unusable (exec stays null)
+    tw_status s = acquire(c, cp->keys, states * 4);
+    if (s == TW_OK)
+        s = acquire(c, cp->lastv, states);
+    if (s == TW_OK)
+        s = acquire(c, cp->table, slots_max * 4);
+    if (s == TW_OK)
+        s = acquire(c, cp->ctr, sizeof(LevelCounters) * 64);
+    if (s == TW_OK)
+        s = acquire(c, cp->ctl, sizeof(twk::CaptureCtl));
+    if (s == TW_OK)
+        s = acquire(c, cp->off_dev, off.size() * 8);
+    if (s == TW_OK)
+        s = acquire(c, cp->out, 64 * 4 + 32);  // order, last state, error flag (cleared as 24 bytes)
+    if (s != TW_OK) {
+        c->err.clear();
+        return nullptr;
+    }
+    // level 0 is the empty set, at keys[off[0]]; the replays never write there
+    if (hipMemcpyAsync(cp->off_dev.p, off.data(), off.size() * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        twk::launch_fill_zero(cp->keys.p, 16, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return nullptr;
+    auto *ctl = (const twk::CaptureCtl *)cp->ctl.p;
+    auto *ctr = (LevelCounters *)cp->ctr.p;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+        return nullptr;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < levels && e == hipSuccess; ++i) {
+        twk::GateArgs ga{ctl, ctr, i};
+        const uint64_t next_cap = off[(size_t)i + 2] - off[(size_t)i + 1];
+        const uint64_t slots = ((uint64_t)((double)next_cap / kCaptureLoad) + 64 + 63) / 64 * 64;
+        e = twk::launch_prep_gated(ga, cp->table.p, slots * 4, c->stream);
+        if (e != hipSuccess)
+            break;
+        twk::LevelArgs a{};
+        a.in = (const uint32_t *)cp->keys.p + off[(size_t)i];
+        a.out = (uint32_t *)cp->keys.p + off[(size_t)i + 1];
+        a.out_lastv = (uint8_t *)cp->lastv.p + off[(size_t)i + 1];
+        a.out_cap = next_cap;
+        a.table = cp->table.p;
+        a.table_slots = slots;
+        a.allowed = ~0ull;  // the replay takes it from the control block
+        a.adj = (const uint64_t *)c->d_adj.p;
+        a.n = n;
+        a.ctr = ctr + i;
+        a.max_probe = (uint32_t)std::min<uint64_t>(slots, 1u << 16);
+        a.read_first = c->opt.probe == 1 ? 0 : 1;
+        a.key_bytes = 4;
+        const uint64_t this_cap = off[(size_t)i + 1] - off[(size_t)i];
+        const uint64_t waves = (this_cap + 63) / 64;
+        uint64_t blocks = (waves + twk::kWavesPerBlock - 1) / twk::kWavesPerBlock;
+        blocks = std::min<uint64_t>(std::max<uint64_t>(blocks, 1), (uint64_t)c->cu_count * 8);
+        e = twk::launch_expand_gated(a, ga, (unsigned)blocks, c->stream);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+    if (e != hipSuccess || e2 != hipSuccess || !graph) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    cp->graph = graph;
+    if (hipGraphInstantiate(&cp->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        cp->exec = nullptr;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return cp;
+}
+
+// decide(k) by one replay of the captured loop; counters as run_decide's.
+tw_status captured_decide(tw_ctx *c, Captured &cp, const Graph &g, int k, uint64_t allowed, int *yes,
+                          RunStats &rs)
+{
+    const int n = g.n;
+    const int L = std::max(0, n - k - 1);
+    rs.decisions++;
+    if (L == 0) {
+        *yes = 1;
+        rs.run_peak = 1;
+        return TW_OK;
+    }
+    CapHost *h = (CapHost *)c->h_cap;
+    h->ctl.k = k;
+    h->ctl.L = L;
+    h->ctl.allowed = allowed;
+    HIP_TRY(c, hipMemcpyAsync(c->d_adj.p, g.rows, sizeof(uint64_t) * 64, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(cp.ctl.p, &h->ctl, sizeof h->ctl, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipGraphLaunch(cp.exec, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(h->ctr, cp.ctr.p, sizeof(LevelCounters) * (size_t)L, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    rs.launches++;
+    uint64_t cur = 1, run_peak = 1;
+    int i = 0;
+    for (; i < L; ++i) {
+        const LevelCounters &lc = h->ctr[i];
+        if (lc.overflow)
+            return kNotCaptured;
+        const uint64_t in_count = cur, out_count = lc.out_count;
+        rs.states_expanded += in_count;
+        rs.expansions += in_count * (uint64_t)(n - i);
+        rs.successors += lc.successors;
+        rs.unique += out_count;
+        rs.levels++;
+        rs.peak = std::max(rs.peak, std::max(out_count, in_count));
+        run_peak = std::max(run_peak, out_count);
+        cur = out_count;
+        if (out_count == 0)
+            break;
+    }
+    rs.run_peak = run_peak;
+    *yes = (i >= L && cur > 0) ? 1 : 0;
+    return TW_OK;
+}
+
+// The order of the YES replay just run at bound k on (possibly augmented) g.
+tw_status captured_order(tw_ctx *c, Captured &cp, const Graph &g, int k, int32_t *order)
+{
+    const int n = g.n;
+    const int L = std::max(0, n - k - 1);
+    CapHost *h = (CapHost *)c->h_cap;
+    uint64_t SL = 0;
+    if (L > 0) {
+        twk::BacktrackArgs b{};
+        b.keys = cp.keys.p;
+        b.lastv = (const uint8_t *)cp.lastv.p;
+        b.off = (const uint64_t *)cp.off_dev.p;
+        b.ctl = (const twk::CaptureCtl *)cp.ctl.p;
+        b.ctr = (const LevelCounters *)cp.ctr.p;
+        b.order = (int32_t *)cp.out.p;
+        b.last_state = (uint64_t *)((char *)cp.out.p + 256);
+        b.err = (int32_t *)((char *)cp.out.p + 264);
+        HIP_TRY(c, twk::launch_zero_counters((LevelCounters *)((char *)cp.out.p + 256), c->stream));
+        HIP_TRY(c, twk::launch_backtrack(b, 4, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(h->order, cp.out.p, 256 + 16, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (h->err)
+            return fail(c, TW_EDEVICE, "captured backtrack: a predecessor is missing");
+        SL = h->last_state;
+    }
+    int t = 0;
+    for (; t < L; ++t) {
+        const int v = h->order[t];
+        if (v < 0 || v >= n || !((SL >> v) & 1ull))
+            return fail(c, TW_EDEVICE, "captured backtrack: bad vertex %d at step %d", v, t);
+        order[t] = v;
+    }
+    for (int v = 0; v < n; ++v)
+        if (!((SL >> v) & 1ull))
+            order[t++] = v;
+    if (t != n || popc(SL) != L)
+        return fail(c, TW_EDEVICE, "captured backtrack produced %d of %d vertices", t, n);
+    const int w = fill_in_width(g, order);
+    if (w < 0 || w > k)
+        return fail(c, TW_EDEVICE, "captured order has width %d > %d", w, k);
+    return TW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graphs of up to 126 vertices: states of two words (vertices 0..63, 64..125).
+// The level loop, duplicate removal, overflow replay and order rebuild are
+// those of the 64-vertex path (exact duplicate removal only); the table slot
+// layout that limits n to 126 is described with the kernel.
+// ---------------------------------------------------------------------------
+constexpr int kWideMaxN = 126;
+
+struct V2 {
+    uint64_t w[2] = {0, 0};
+    bool has(int v) const { return (w[v >> 6] >> (v & 63)) & 1ull; }
+    void set(int v) { w[v >> 6] |= 1ull << (v & 63); }
+    void clear(int v) { w[v >> 6] &= ~(1ull << (v & 63)); }
+    int count() const { return popc(w[0]) + popc(w[1]); }
+    bool any() const { return (w[0] | w[1]) != 0; }
+    V2 operator&(const V2 &o) const { V2 r; r.w[0] = w[0] & o.w[0]; r.w[1] = w[1] & o.w[1]; return r; }
+    V2 operator|(const V2 &o) const { V2 r; r.w[0] = w[0] | o.w[0]; r.w[1] = w[1] | o.w[1]; return r; }
+    V2 operator~() const { V2 r; r.w[0] = ~w[0]; r.w[1] = ~w[1]; return r; }
+    int lowest() const { return w[0] ? __builtin_ctzll(w[0]) : 64 + __builtin_ctzll(w[1]); }
+};
+
+struct GraphW {
+    int n = 0;
+    V2 rows[128];
+};
+
+V2 all_of(int n)
+{
+    V2 a;
+    for (int v = 0; v < n; ++v)
+        a.set(v);
+    return a;
+}
+
+tw_status validate_wide(tw_ctx *c, const tw_graph128 *g, GraphW &out)
+{
+    if (!g || !g->adj)
+        return fail(c, TW_EINVAL, "graph or adjacency pointer is NULL");
+    if (g->n < 1 || g->n > kWideMaxN)
+        return fail(c, TW_EINVAL, "n=%u outside 1..%d", g->n, kWideMaxN);
+    out.n = (int)g->n;
+    const V2 all = all_of(out.n);
+    for (int i = 0; i < out.n; ++i) {
+        V2 r;
+        r.w[0] = g->adj[2 * i];
+        r.w[1] = g->adj[2 * i + 1];
+        if ((r & ~all).any())
+            return fail(c, TW_EINVAL, "row %d has bits at positions >= n", i);
+        if (r.has(i))
+            return fail(c, TW_EINVAL, "self-loop at vertex %d", i);
+        out.rows[i] = r;
+    }
+    for (int i = 0; i < out.n; ++i)
+        for (int j = 0; j < out.n; ++j)
+            if (out.rows[i].has(j) != out.rows[j].has(i))
+                return fail(c, TW_EINVAL, "adjacency not symmetric at (%d,%d)", i, j);
+    return TW_OK;
+}
+
+// Minor-min-width (§3.3) with the tie-breaks of mmw_bound.
+int mmw_bound_wide(const GraphW &g)
+{
+    V2 nb[128];
+    V2 alive = all_of(g.n);
+    for (int v = 0; v < g.n; ++v)
+        nb[v] = g.rows[v];
+    int lb = 0;
+    while (alive.count() >= 2) {
+        int d1 = 1 << 20, d2 = 1 << 20, v = -1;
+        for (int x = 0; x < g.n; ++x) {
+            if (!alive.has(x))
+                continue;
+            const int d = nb[x].count();
+            if (d < d1) {
+                d2 = d1;
+                d1 = d;
+                v = x;
+            } else if (d < d2) {
+                d2 = d;
+            }
+        }
+        lb = std::max(lb, d2);
+        if (d1 == 0) {
+            alive.clear(v);
+            continue;
+        }
+        int u = -1, du = 1 << 20;
+        for (int x = 0; x < g.n; ++x)
+            if (nb[v].has(x) && nb[x].count() < du) {
+                du = nb[x].count();
+                u = x;
+            }
+        for (int w = 0; w < g.n; ++w) {
+            if (!nb[v].has(w))
+                continue;
+            nb[w].clear(v);
+            if (w != u) {
+                nb[w].set(u);
+                nb[u].set(w);
+            }
+        }
+        nb[v] = V2{};
+        alive.clear(v);
+    }
+    return lb;
+}
+
+int fill_in_width_wide(const GraphW &g, const int32_t *order)
+{
+    V2 adj[128], seen;
+    for (int v = 0; v < g.n; ++v)
+        adj[v] = g.rows[v];
+    for (int t = 0; t < g.n; ++t) {
+        const int v = order[t];
+        if (v < 0 || v >= g.n || seen.has(v))
+            return -1;
+        seen.set(v);
+    }
+    V2 alive = seen;
+    int width = 0;
+    for (int t = 0; t < g.n; ++t) {
+        const int v = order[t];
+        V2 N = adj[v] & alive;
+        N.clear(v);
+        width = std::max(width, N.count());
+        for (int u = 0; u < g.n; ++u)
+            if (N.has(u)) {
+                V2 add = N;
+                add.clear(u);
+                adj[u] = adj[u] | add;
+            }
+        alive.clear(v);
+    }
+    return width;
+}
+
+tw_status emit_level_wide(tw_ctx *c, const Sink &sink, int k, int i, const Level &lv, uint64_t expansions,
+                          uint64_t successors)
+{
+    std::vector<uint64_t> keys(2 * lv.count);
+    std::vector<uint8_t> lastv(lv.count, 0);
+    if (lv.count) {
+        HIP_TRY(c, hipMemcpyAsync(keys.data(), lv.keys.p, lv.count * 16, hipMemcpyDeviceToHost, c->stream));
+        if (i > 0)
+            HIP_TRY(c, hipMemcpyAsync(lastv.data(), lv.lastv.p, lv.count, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    tw_level_record rec{};
+    rec.k = k;
+    rec.level = i;
+    rec.count = lv.count;
+    rec.expansions = expansions;
+    rec.successors = successors;
+    rec.states = keys.data();
+    rec.last_v = lastv.data();
+    sink.fn(&rec, sink.user);
+    return TW_OK;
+}
+
+// decide(k) for a graph of up to 126 vertices (Listing 1, exact duplicate
+// removal).  keep_all: every level stays on the device, trimmed to its size.
+tw_status run_decide_wide(tw_ctx *c, const GraphW &g, int k, bool keep_all, const Sink *sink,
+                          std::vector<Level> &levels, int *yes, RunStats &rs, V2 allowed)
+{
+    const int n = g.n;
+    const int L = std::max(0, n - k - 1);
+    rs.decisions++;
+    free_levels(c, levels);
+    levels.assign(1, Level{});
+    {
+        Level &l0 = levels[0];
+        tw_status s = acquire(c, l0.keys, 16);
+        if (s != TW_OK)
+            return s;
+        HIP_TRY(c, twk::launch_fill_zero(l0.keys.p, 16, c->stream));
+        l0.count = 1;
+    }
+    if (sink && sink->fn) {
+        tw_status s = emit_level_wide(c, *sink, k, 0, levels[0], 0, 0);
+        if (s != TW_OK)
+            return s;
+    }
+    {
+        tw_status s = acquire(c, c->d_adj_wide, 128 * 16);
+        if (s != TW_OK)
+            return s;
+        std::vector<uint64_t> rows(256, 0);
+        for (int v = 0; v < n; ++v) {
+            rows[2 * v] = g.rows[v].w[0];
+            rows[2 * v + 1] = g.rows[v].w[1];
+        }
+        HIP_TRY(c, hipMemcpyAsync(c->d_adj_wide.p, rows.data(), rows.size() * 8, hipMemcpyHostToDevice,
+                                  c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    const float alpha = (c->opt.load_factor > 0.f && c->opt.load_factor <= 0.9f) ? c->opt.load_factor : 0.25f;
+    const size_t dev_free = free_device_bytes(c);
+    double growth = (double)n;
+    Buf scratch_keys, scratch_lastv;
+    tw_status status = TW_OK;
+    uint64_t cur = 1, run_peak = 1;
+    int i = 0;
+    for (; i < L; ++i) {
+        Level &in = levels.back();
+        const uint64_t in_count = in.count;
+        const uint64_t pairs = in_count > UINT64_MAX / 128 ? UINT64_MAX : in_count * (uint64_t)(n - i);
+        const uint64_t bound = std::min<uint64_t>(binom_sat(n, i + 1), pairs);
+        uint64_t guess = c->opt.capacity_override
+                             ? c->opt.capacity_override
+                             : (uint64_t)std::min<double>((double)in_count * std::max(1.0, growth) * 1.3 + 4096.0,
+                                                          1.8e19);
+        guess = std::max<uint64_t>(std::min(guess, bound), 1);
+        float a_eff = std::max(alpha, std::min(0.5f, (float)((double)guess * 16 * 3.0 / (double)dev_free)));
+        uint64_t out_count = 0, succ = 0;
+        bool injected = false;
+        for (;;) {
+            if (c->opt.max_states && guess > c->opt.max_states)
+                guess = std::max<uint64_t>(c->opt.max_states, 1);
+            const uint64_t slots = ((uint64_t)((double)guess / a_eff) + 64 + 63) / 64 * 64;
+            uint64_t out_cap = std::min<uint64_t>(bound, std::max<uint64_t>(guess, (uint64_t)(0.6 * (double)slots)));
+            if (c->opt.max_states)
+                out_cap = std::min<uint64_t>(out_cap, c->opt.max_states);
+            status = acquire(c, c->table, slots * 16);
+            if (status == TW_OK)
+                status = acquire(c, scratch_keys, out_cap * 16);
+            if (status == TW_OK)
+                status = acquire(c, scratch_lastv, out_cap);
+            if (status == TW_ENOMEM && a_eff < 0.8f) {
+                release(c, scratch_keys);
+                release(c, scratch_lastv);
+                release(c, c->table);
+                drop_cache(c);
+                a_eff = 0.8f;
+                status = TW_OK;
+                c->err.clear();
+                continue;
+            }
+            if (status != TW_OK)
+                goto done;
+            HIP_TRY(c, twk::launch_fill_empty(c->table.p, slots * 16, c->stream));
+            HIP_TRY(c, twk::launch_zero_counters((LevelCounters *)c->d_ctr.p, c->stream));
+            twk::LevelArgs a{};
+            a.in = in.keys.p;
+            a.in_count = in_count;
+            a.out = scratch_keys.p;
+            a.out_lastv = (uint8_t *)scratch_lastv.p;
+            a.out_cap = out_cap;
+            a.table = c->table.p;
+            a.table_slots = slots;
+            a.allowed = allowed.w[0];
+            a.adj = (const uint64_t *)c->d_adj_wide.p;
+            a.n = n;
+            a.k = k;
+            a.ctr = (LevelCounters *)c->d_ctr.p;
+            a.max_probe = (uint32_t)std::min<uint64_t>(slots, 1u << 16);
+            a.key_bytes = 16;
+            const uint64_t waves = (in_count + 63) / 64;
+            uint64_t blocks = (waves + twk::kWavesPerBlock - 1) / twk::kWavesPerBlock;
+            blocks = std::min<uint64_t>(std::max<uint64_t>(blocks, 1), (uint64_t)c->cu_count * 8);
+            if (c->opt.timing)
+                HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+            HIP_TRY(c, twk::launch_expand_wide(a, allowed.w[1], (unsigned)blocks, c->stream));
+            if (c->opt.timing)
+                HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr.p, sizeof(LevelCounters), hipMemcpyDeviceToHost,
+                                      c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            rs.launches++;
+            if (c->opt.timing) {
+                float ms = 0.f;
+                HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+                rs.kernel_seconds += ms * 1e-3;
+            }
+            LevelCounters h = *c->h_ctr;
+            if (c->opt.fault_inject_level == i + 1 && !injected) {
+                injected = true;
+                h.overflow = 1;
+            }
+            if (!h.overflow) {
+                out_count = h.out_count;
+                succ = h.successors;
+                break;
+            }
+            rs.retries++;
+            if (c->opt.max_states && out_cap >= c->opt.max_states) {
+                status = fail(c, TW_ECAPACITY, "level %d needs more than max_states=%llu states", i + 1,
+                              (unsigned long long)c->opt.max_states);
+                goto done;
+            }
+            if (out_cap >= bound && (double)slots * 0.8 >= (double)bound && !injected) {
+                status = fail(c, TW_EDEVICE, "overflow at level %d with capacity at its bound", i + 1);
+                goto done;
+            }
+            guess = std::min<uint64_t>(bound, std::max<uint64_t>(guess * 2, (uint64_t)(1.3 * (double)h.out_count)));
+            a_eff = std::max(a_eff * 0.75f, 0.1f);
+        }
+        rs.states_expanded += in_count;
+        rs.expansions += in_count * (uint64_t)(n - i);
+        rs.successors += succ;
+        rs.unique += out_count;
+        rs.levels++;
+        rs.peak = std::max(rs.peak, std::max(out_count, in_count));
+        run_peak = std::max(run_peak, out_count);
+        growth = in_count ? (double)out_count / (double)in_count : 1.0;
+        {
+            Level nl;
+            nl.count = out_count;
+            if (keep_all || sink) {
+                status = acquire(c, nl.keys, std::max<uint64_t>(out_count, 1) * 16);
+                if (status == TW_OK)
+                    status = acquire(c, nl.lastv, std::max<uint64_t>(out_count, 1));
+                if (status != TW_OK)
+                    goto done;
+                if (out_count) {
+                    HIP_TRY(c, hipMemcpyAsync(nl.keys.p, scratch_keys.p, out_count * 16, hipMemcpyDeviceToDevice,
+                                              c->stream));
+                    HIP_TRY(c, hipMemcpyAsync(nl.lastv.p, scratch_lastv.p, out_count, hipMemcpyDeviceToDevice,
+                                              c->stream));
+                }
+            } else {
+                nl.keys = scratch_keys;
+                nl.lastv = scratch_lastv;
+                scratch_keys = Buf{};
+                scratch_lastv = Buf{};
+            }
+            if (sink && sink->fn) {
+                status = emit_level_wide(c, *sink, k, i + 1, nl, in_count * (uint64_t)(n - i), succ);
+                if (status != TW_OK) {
+                    release(c, nl.keys);
+                    release(c, nl.lastv);
+                    goto done;
+                }
+            }
+            if (!keep_all) {
+                Level &old = levels.back();
+                if (!sink) {
+                    scratch_keys = old.keys;
+                    scratch_lastv = old.lastv;
+                    old.keys = Buf{};
+                    old.lastv = Buf{};
+                } else {
+                    release(c, old.keys);
+                    release(c, old.lastv);
+                }
+                levels.back() = nl;
+            } else {
+                levels.push_back(nl);
+            }
+        }
+        cur = out_count;
+        if (out_count == 0)
+            break;
+    }
+done:
+    release(c, scratch_keys);
+    release(c, scratch_lastv);
+    rs.run_peak = run_peak;
+    if (status != TW_OK)
+        return status;
+    *yes = (L == 0 || (i >= L && cur > 0)) ? 1 : 0;
+    return TW_OK;
+}
+
+// The order of a YES run whose levels were all kept: follow the creating
+// vertex back from the first state of the last level.
+tw_status reconstruct_wide(tw_ctx *c, const GraphW &g, int k, const std::vector<Level> &levels, int32_t *order)
+{
+    const int n = g.n;
+    const int L = (int)levels.size() - 1;
+    std::vector<int> rev;
+    V2 S, SL;
+    if (L > 0) {
+        uint64_t key[2] = {0, 0};
+        HIP_TRY(c, hipMemcpyAsync(key, levels[L].keys.p, 16, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        S.w[0] = key[0];
+        S.w[1] = key[1];
+        SL = S;
+        uint64_t idx = 0;
+        for (int i = L; i >= 1; --i) {
+            uint8_t v = 0;
+            HIP_TRY(c, hipMemcpyAsync(&v, (const uint8_t *)levels[i].lastv.p + idx, 1, hipMemcpyDeviceToHost,
+                                      c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            if (v >= n || !S.has(v))
+                return fail(c, TW_EDEVICE, "reconstruction: bad last vertex %d at level %d", v, i);
+            rev.push_back(v);
+            S.clear(v);
+            if (i == 1)
+                break;
+            *c->h_find = ~0ull;
+            HIP_TRY(c, hipMemcpyAsync(c->d_find.p, c->h_find, 8, hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, twk::launch_find_wide(levels[i - 1].keys.p, levels[i - 1].count, S.w[0], S.w[1],
+                                             (unsigned long long *)c->d_find.p, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(c->h_find, c->d_find.p, 8, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            idx = *c->h_find;
+            if (idx == ~0ull)
+                return fail(c, TW_EDEVICE, "reconstruction: predecessor missing at level %d", i - 1);
+        }
+    }
+    int t = 0;
+    for (int r = (int)rev.size() - 1; r >= 0; --r)
+        order[t++] = rev[(size_t)r];
+    for (int v = 0; v < n; ++v)
+        if (!SL.has(v))
+            order[t++] = v;
+    if (t != n)
+        return fail(c, TW_EDEVICE, "reconstruction produced %d of %d vertices", t, n);
+    const int w = fill_in_width_wide(g, order);
+    if (w < 0 || w > k)
+        return fail(c, TW_EDEVICE, "reconstructed order has width %d > %d", w, k);
+    return TW_OK;
+}
+
+// tw and an order: ascending bounds from the minor-min-width bound; each YES
+// keeps its levels while they fit the keep budget, else the search is run
+// again restricted to the subsets of one last-level state.
+tw_status solve_wide(tw_ctx *c, const GraphW &g, int32_t *out_tw, int32_t *out_order, RunStats &rs)
+{
+    const int n = g.n;
+    const V2 all = all_of(n);
+    for (int k = mmw_bound_wide(g); k < n; ++k) {
+        std::vector<Level> levels;
+        int yes = 0;
+        const int L = std::max(0, n - k - 1);
+        // a YES needs its levels for the order; keep them unless they outgrow the budget
+        tw_status s = run_decide_wide(c, g, k, false, nullptr, levels, &yes, rs, all);
+        if (s != TW_OK) {
+            free_levels(c, levels);
+            return s;
+        }
+        if (!yes) {
+            free_levels(c, levels);
+            continue;
+        }
+        V2 SL;
+        if (L > 0) {
+            uint64_t key[2] = {0, 0};
+            HIP_TRY(c, hipMemcpyAsync(key, levels.back().keys.p, 16, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            SL.w[0] = key[0];
+            SL.w[1] = key[1];
+        }
+        free_levels(c, levels);
+        // the levels restricted to subsets of one last-level state are small: keep them all
+        int yes2 = 0;
+        s = run_decide_wide(c, g, k, true, nullptr, levels, &yes2, rs, L > 0 ? SL : all);
+        if (s == TW_OK && !yes2)
+            s = fail(c, TW_EDEVICE, "restricted search lost the state it started from");
+        if (s == TW_OK)
+            s = reconstruct_wide(c, g, k, levels, out_order);
+        free_levels(c, levels);
+        if (s != TW_OK)
+            return s;
+        *out_tw = k;
+        return TW_OK;
+    }
+    return fail(c, TW_EDEVICE, "no bound below n gave YES");
+}
+
 // Search from bound k0 (lb <= k0 <= n-1): after a YES at k (its order kept)
 // move down, after a NO move up, until a YES at t meets a NO at t-1 or t = lb.
 // With k0 = lb this is the ascending search of Listing 1 started at the
@@ -1026,9 +1837,44 @@ tw_status solve_one(tw_ctx *c, const Graph &g, const Reduction *red, int lb, int
         oc->start_k = k;
     std::vector<int32_t> order((size_t)n);
     std::vector<Level> levels;
+    Captured *cap = capture_for(c, g);
     while (best_yes > known_no + 1) {
         int yes = 0;
+        if (oc && rs.decisions > d0)
+            oc->peak_any = std::max(oc->peak_any, rs.run_peak);
+        if (cap) {
+            // the level loop as one graph replay per bound
+            tw_status s = TW_OK;
+            if (red && k < red->clique_size - 1)
+                rs.decisions++;  // NO without a search below the clique bound
+            else
+                s = captured_decide(c, *cap, red ? augmented(g, *red, k) : g, k, red ? ~red->clique : ~0ull,
+                                    &yes, rs);
+            if (s == kNotCaptured) {
+                rs.decisions--;
+                cap = nullptr;  // this bound (and the rest) on the host-driven loop
+                continue;
+            }
+            if (s == TW_OK && yes)
+                s = captured_order(c, *cap, red ? augmented(g, *red, k) : g, k, order.data());
+            if (s != TW_OK)
+                return s;
+            if (yes) {
+                best_yes = k;
+                peak_yes = rs.run_peak;
+                std::copy(order.begin(), order.end(), out_order);
+                k = best_yes - 1;
+            } else {
+                known_no = std::max(known_no, k);
+                k = known_no + 1;
+            }
+            if (k >= best_yes || k <= known_no)
+                break;
+            continue;
+        }
         tw_status s = decide_checked(c, g, red, k, kKeepIfSmall, levels, &yes, rs);
+        if (oc)
+            oc->peak_any = std::max(oc->peak_any, rs.run_peak);
         if ((s == TW_ECAPACITY || s == TW_ENOMEM) && k > known_no + 1) {
             // a bound above the ascending frontier (a learned start) outgrew the
             // state cap or memory: continue upwards from the frontier instead
@@ -1088,6 +1934,7 @@ tw_status solve_one(tw_ctx *c, const Graph &g, const Reduction *red, int lb, int
         return fail(c, TW_EDEVICE, "order width %d differs from treewidth %d", w, best_yes);
     *out_tw = best_yes;
     if (oc) {
+        oc->peak_any = std::max(oc->peak_any, rs.run_peak);
         oc->peak_yes = peak_yes;
         oc->expansions = rs.expansions - e0;
         oc->states = rs.states_expanded - s0;
@@ -1097,16 +1944,27 @@ tw_status solve_one(tw_ctx *c, const Graph &g, const Reduction *red, int lb, int
     return TW_OK;
 }
 
+// Trace mode of the batched search (tw_trace_batch): per graph, up to
+// max_records level records; nrecords[t] is what graph t's last batched
+// attempt wrote (or wanted, when above max_records).
+struct BatchTrace {
+    uint32_t max_records = 0;
+    uint64_t first_arena = 0;     // arena of the first attempt (0: as tw_solve_batch)
+    tw_batch_level *records = nullptr;
+    uint32_t *nrecords = nullptr;
+};
+
 // One batched solve (level rounds or one persistent launch) over the graphs ids[0..B): start bound k0s[t] and
 // arena of arena[t] states for graph ids[t].  Graphs that finish get their
 // tw, order and outcome; graphs whose arena or table filled up are appended
 // to single_ids for the tw_solve path.
+
 tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<Reduction> *reds,
                        const std::vector<int> &lbs,
                        const std::vector<int> &k0s, const std::vector<uint64_t> &arenas,
                        const std::vector<int> &ids, int32_t *out_tw, int32_t *out_orders,
                        const std::vector<size_t> &offs, tw_status *out_status, std::vector<int> &single_ids,
-                       std::vector<GraphOutcome> &outcomes, RunStats &rs)
+                       std::vector<GraphOutcome> &outcomes, RunStats &rs, const BatchTrace *trace)
 {
     const size_t B = ids.size();
     if (!B)
@@ -1127,8 +1985,9 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
         slot_total += slots[b];
     }
     const size_t job_bytes = (job_cap * sizeof(twk::BatchJob) + 15) / 16 * 16;
-    Buf d_graphs, d_jobs, d_q, d_keys, d_lastv, d_parent, d_table, d_paths;
+    Buf d_graphs, d_jobs, d_q, d_keys, d_lastv, d_parent, d_table, d_paths, d_trace;
     auto cleanup = [&]() {
+        release(c, d_trace);
         release(c, d_paths);
         release(c, d_parent);
         release(c, d_graphs);
@@ -1153,6 +2012,9 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
         s = acquire(c, d_table, slot_total * sizeof(uint64_t));
     if (s == TW_OK && reds)
         s = acquire(c, d_paths, B * 64 * 64);
+    const uint64_t tcap = trace ? trace->max_records : 0;
+    if (s == TW_OK && tcap)
+        s = acquire(c, d_trace, B * tcap * sizeof(twk::BatchTraceRec));
     if (s != TW_OK) {
         cleanup();
         return s;
@@ -1191,6 +2053,11 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
             G.order[v] = v < g.n ? v : -1;
         G.allowed = ~0ull;
         G.paths = nullptr;
+        G.fault_level = c->opt.fault_inject_level;
+        if (tcap) {
+            G.trace = (twk::BatchTraceRec *)d_trace.p + b * tcap;
+            G.trace_cap = (uint32_t)tcap;
+        }
         if (reds) {
             const Reduction &r = (*reds)[(size_t)t];
             G.allowed = ~r.clique;
@@ -1269,7 +2136,19 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
     HIP_TRY(c, hipMemcpyAsync(hg.data(), d_graphs.p, B * sizeof(twk::BatchGraph), hipMemcpyDeviceToHost,
                               c->stream));
     HIP_TRY(c, hipMemcpyAsync(&hq, d_q.p, sizeof hq, hipMemcpyDeviceToHost, c->stream));
+    std::vector<twk::BatchTraceRec> hrec(B * tcap);
+    if (tcap)
+        HIP_TRY(c, hipMemcpyAsync(hrec.data(), d_trace.p, hrec.size() * sizeof(twk::BatchTraceRec),
+                                  hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    static_assert(sizeof(twk::BatchTraceRec) == sizeof(tw_batch_level), "trace record layout");
+    if (tcap)
+        for (size_t b = 0; b < B; ++b) {
+            const int t = ids[b];
+            trace->nrecords[t] = hg[b].status == twk::kBatchDone ? hg[b].trace_len : 0;
+            std::memcpy(trace->records + (size_t)t * tcap, hrec.data() + b * tcap,
+                        std::min<uint64_t>(hg[b].trace_len, tcap) * sizeof(twk::BatchTraceRec));
+        }
     rs.launches++;
     if (c->opt.timing) {
         float ms = 0.f;
@@ -1306,6 +2185,7 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
         out_status[t] = TW_OK;
         GraphOutcome &oc = outcomes[(size_t)t];
         oc.peak_yes = G.peak_yes;
+        oc.peak_any = G.peak;
         oc.expansions = G.expansions;
         oc.states = G.states;
         oc.start_k = k0s[(size_t)t];
@@ -1321,12 +2201,11 @@ tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vect
                     const std::vector<int> &k0s, const std::vector<uint64_t> &arena_of,
                     const std::vector<int> &ids, int32_t *out_tw, int32_t *out_orders,
                     const std::vector<size_t> &offs, tw_status *out_status, std::vector<int> &single_ids,
-                    std::vector<GraphOutcome> &outcomes, RunStats &rs)
+                    std::vector<GraphOutcome> &outcomes, RunStats &rs, const BatchTrace *trace)
 {
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
-        free_b = (size_t)32 << 30;
-    const uint64_t budget = std::max<uint64_t>((uint64_t)(free_b / 2), (uint64_t)1 << 30);
+    const size_t free_b = free_device_bytes(c);
+    const uint64_t budget = c->carve ? (uint64_t)(free_b * 0.9)
+                                     : std::max<uint64_t>((uint64_t)(free_b / 2), (uint64_t)1 << 30);
     std::vector<int> group;
     std::vector<uint64_t> arenas;
     uint64_t used = 0;
@@ -1336,9 +2215,15 @@ tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vect
             need = arena_of[(size_t)ids[q]] * 13 + arena_of[(size_t)ids[q]] * 8 + 4096;
         if (q == ids.size() || (!group.empty() && used + need > budget)) {
             tw_status s = batch_launch(c, graphs, reds, lbs, k0s, arenas, group, out_tw, out_orders, offs,
-                                       out_status, single_ids, outcomes, rs);
-            if (s != TW_OK)
+                                       out_status, single_ids, outcomes, rs, trace);
+            if (s == TW_ENOMEM) {
+                // device memory taken meanwhile (the single-graph path may run
+                // concurrently on a second stream): these graphs go that way too
+                single_ids.insert(single_ids.end(), group.begin(), group.end());
+                c->err.clear();
+            } else if (s != TW_OK) {
                 return s;
+            }
             group.clear();
             arenas.clear();
             used = 0;
@@ -1461,6 +2346,14 @@ tw_status tw_ctx_create(const tw_options *options, tw_ctx **out)
         delete c;
         return TW_EINVAL;
     }
+    if (c->opt.workspace && c->opt.workspace_bytes) {
+        c->ws.reset(c->opt.workspace, c->opt.workspace_bytes);
+        c->carve = &c->ws;
+    }
+    if (c->opt.fault_inject_level < 0) {
+        delete c;
+        return TW_EINVAL;
+    }
     c->device = c->opt.device;
     auto bad = [&](hipError_t e) {
         (void)e;
@@ -1483,6 +2376,15 @@ tw_status tw_ctx_create(const tw_options *options, tw_ctx **out)
     }
     if (hipHostMalloc((void **)&c->h_ctr, sizeof(LevelCounters), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->h_find, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+        tw_ctx_destroy(c);
+        return TW_ENOMEM;
+    }
+    if (c->opt.capture != TW_CAPTURE_AUTO && c->opt.capture != TW_CAPTURE_OFF) {
+        tw_ctx_destroy(c);
+        return TW_EINVAL;
+    }
+    if (c->opt.capture == TW_CAPTURE_AUTO &&
+        hipHostMalloc(&c->h_cap, sizeof(CapHost), hipHostMallocDefault) != hipSuccess) {
         tw_ctx_destroy(c);
         return TW_ENOMEM;
     }
@@ -1518,7 +2420,13 @@ void tw_ctx_destroy(tw_ctx *c)
         tw_mpnn_destroy(c->net);
     if (c->stream)
         (void)hipStreamSynchronize(c->stream);
+    for (Captured *cp : c->captured)
+        destroy_captured(c, cp);
+    c->captured.clear();
+    if (c->h_cap)
+        (void)hipHostFree(c->h_cap);
     release(c, c->d_adj);
+    release(c, c->d_adj_wide);
     release(c, c->d_ctr);
     release(c, c->d_find);
     release(c, c->table);
@@ -1561,10 +2469,10 @@ tw_status tw_decide(tw_ctx *c, const tw_graph *gr, int32_t k, int32_t *out_yes, 
         red = reduction_of(g, -1);
     s = decide_checked(c, g, c->opt.reductions ? &red : nullptr, k, kKeepPair, levels, &yes, rs);
     free_levels(c, levels);
+    add_stats(stats, rs, now_s() - t0);  // the work done, also when the call fails
     if (s != TW_OK)
         return s;
     *out_yes = yes;
-    add_stats(stats, rs, now_s() - t0);
     return TW_OK;
 }
 
@@ -1634,9 +2542,113 @@ tw_status tw_solve(tw_ctx *c, const tw_graph *gr, int32_t *out_tw, int32_t *out_
     return TW_OK;
 }
 
-tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t *out_tw,
-                         int32_t *out_orders, tw_status *out_status, tw_graph_stats *out_graph_stats,
-                         tw_stats *stats)
+tw_status tw_decide128(tw_ctx *c, const tw_graph128 *gr, int32_t k, int32_t *out_yes, tw_stats *stats)
+{
+    if (!c || !out_yes)
+        return TW_EINVAL;
+    c->err.clear();
+    GraphW g;
+    tw_status s = validate_wide(c, gr, g);
+    if (s != TW_OK)
+        return s;
+    if (k < 0)
+        return fail(c, TW_EINVAL, "k=%d < 0", k);
+    if (hipSetDevice(c->device) != hipSuccess)
+        return fail(c, TW_EDEVICE, "hipSetDevice failed");
+    const double t0 = now_s();
+    RunStats rs;
+    std::vector<Level> levels;
+    int yes = 0;
+    s = run_decide_wide(c, g, k, false, nullptr, levels, &yes, rs, all_of(g.n));
+    free_levels(c, levels);
+    if (s != TW_OK)
+        return s;
+    *out_yes = yes;
+    add_stats(stats, rs, now_s() - t0);
+    return TW_OK;
+}
+
+tw_status tw_trace_decide128(tw_ctx *c, const tw_graph128 *gr, int32_t k,
+                             void (*sink)(const tw_level_record *, void *), void *user, int32_t *out_yes)
+{
+    if (!c || !sink)
+        return TW_EINVAL;
+    c->err.clear();
+    GraphW g;
+    tw_status s = validate_wide(c, gr, g);
+    if (s != TW_OK)
+        return s;
+    if (k < 0)
+        return fail(c, TW_EINVAL, "k=%d < 0", k);
+    if (hipSetDevice(c->device) != hipSuccess)
+        return fail(c, TW_EDEVICE, "hipSetDevice failed");
+    RunStats rs;
+    std::vector<Level> levels;
+    Sink sk;
+    sk.fn = sink;
+    sk.user = user;
+    int yes = 0;
+    s = run_decide_wide(c, g, k, false, &sk, levels, &yes, rs, all_of(g.n));
+    free_levels(c, levels);
+    if (s != TW_OK)
+        return s;
+    if (out_yes)
+        *out_yes = yes;
+    return TW_OK;
+}
+
+tw_status tw_solve128(tw_ctx *c, const tw_graph128 *gr, int32_t *out_tw, int32_t *out_order, tw_stats *stats)
+{
+    if (!c || !out_tw || !out_order)
+        return TW_EINVAL;
+    c->err.clear();
+    GraphW g;
+    tw_status s = validate_wide(c, gr, g);
+    if (s != TW_OK)
+        return s;
+    if (hipSetDevice(c->device) != hipSuccess)
+        return fail(c, TW_EDEVICE, "hipSetDevice failed");
+    const double t0 = now_s();
+    RunStats rs;
+    s = solve_wide(c, g, out_tw, out_order, rs);
+    if (s != TW_OK)
+        return s;
+    const int w = fill_in_width_wide(g, out_order);
+    if (w != *out_tw)
+        return fail(c, TW_EDEVICE, "order width %d differs from treewidth %d", w, *out_tw);
+    add_stats(stats, rs, now_s() - t0);
+    return TW_OK;
+}
+
+tw_status tw_mmw128(const tw_graph128 *gr, int32_t *out_lb)
+{
+    if (!out_lb)
+        return TW_EINVAL;
+    GraphW g;
+    tw_status s = validate_wide(nullptr, gr, g);
+    if (s != TW_OK)
+        return s;
+    *out_lb = mmw_bound_wide(g);
+    return TW_OK;
+}
+
+tw_status tw_order_width128(const tw_graph128 *gr, const int32_t *order, int32_t *out_width)
+{
+    if (!order || !out_width)
+        return TW_EINVAL;
+    GraphW g;
+    tw_status s = validate_wide(nullptr, gr, g);
+    if (s != TW_OK)
+        return s;
+    *out_width = fill_in_width_wide(g, order);
+    return TW_OK;
+}
+
+namespace {
+
+tw_status solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t *out_tw, int32_t *out_orders,
+                      tw_status *out_status, tw_graph_stats *out_graph_stats, tw_stats *stats,
+                      const BatchTrace *trace)
 {
     if (!c || (count && (!gs || !out_tw || !out_orders || !out_status)))
         return TW_EINVAL;
@@ -1656,9 +2668,7 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
     // batch (21 bytes per state: key, creator byte, parent index, table slot), 2^16..2^22
     uint64_t default_arena = c->opt.batch_graph_states;
     if (!default_arena) {
-        size_t free_b = 0, total_b = 0;
-        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
-            free_b = (size_t)16 << 30;
+        const size_t free_b = free_device_bytes(c);
         const uint64_t per = (uint64_t)(free_b / 2) / std::max<uint64_t>(1, count) / 21;
         default_arena = 1ull << 16;
         while (default_arena < (1ull << 22) && default_arena * 2 <= per)
@@ -1718,7 +2728,11 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
     tw_status st = predict_starts(c, graphs, lbs, learned_ids, k0s, arena_of, &too_big);
     if (st != TW_OK)
         return st;
-    if (c->opt.batch_graph_states)
+    const bool library_arena = !c->opt.batch_graph_states || (trace && trace->first_arena);
+    if (trace && trace->first_arena)
+        for (int t : batch_ids)
+            arena_of[(size_t)t] = trace->first_arena;
+    else if (c->opt.batch_graph_states)
         for (int t : batch_ids)
             arena_of[(size_t)t] = c->opt.batch_graph_states;
     else if (c->net) {
@@ -1751,7 +2765,7 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
                 tw_ctx_destroy(ctx);
         }
     } aux;
-    if (!single_ids.empty() && !batch_ids.empty()) {
+    if (!single_ids.empty() && !batch_ids.empty() && !c->carve) {
         tw_options o = c->opt;
         o.stream = nullptr;
         o.k_policy = TW_K_ASCENDING;  // starts are already chosen
@@ -1771,10 +2785,9 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
                                             lbs[(size_t)t], k0s[(size_t)t], &out_tw[t],
                                             out_orders + offs[(size_t)t], aux.rs, &oc);
                     out_status[t] = s;
+                    outcomes[(size_t)t] = oc;
                     if (s != TW_OK)
                         out_tw[t] = -1;
-                    else
-                        outcomes[(size_t)t] = oc;
                     if (s == TW_EDEVICE) {
                         aux.status = s;
                         aux.err = aux.ctx->err;
@@ -1798,13 +2811,13 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
 
     const size_t before = single_ids.size();
     st = batch_run(c, graphs, rp, lbs, k0s, arena_of, batch_ids, out_tw, out_orders, offs, out_status,
-                   single_ids, outcomes, rs);
+                   single_ids, outcomes, rs, trace);
     if (st != TW_OK)
         return st;
     // graphs whose levels outgrew their arena: once more together, with 4x the
     // arena (up to kArenaRetry states), before the one-at-a-time path (level
     // rounds only: the persistent queue measured slower with the retry)
-    if (!c->opt.batch_graph_states && c->opt.batch_schedule == TW_BATCH_ROUNDS && single_ids.size() > before) {
+    if (library_arena && c->opt.batch_schedule == TW_BATCH_ROUNDS && single_ids.size() > before) {
         std::vector<int> retry(single_ids.begin() + (long)before, single_ids.end());
         single_ids.resize(before);
         std::vector<int> again;
@@ -1817,7 +2830,7 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
             }
         }
         st = batch_run(c, graphs, rp, lbs, k0s, arena_of, again, out_tw, out_orders, offs, out_status,
-                       single_ids, outcomes, rs);
+                       single_ids, outcomes, rs, trace);
         if (st != TW_OK)
             return st;
     }
@@ -1827,16 +2840,30 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
                                 k0s[(size_t)t], &out_tw[t],
                                 out_orders + offs[(size_t)t], rs, &oc);
         out_status[t] = s;
+        outcomes[(size_t)t] = oc;
         if (s != TW_OK)
             out_tw[t] = -1;
-        else
-            outcomes[(size_t)t] = oc;
         if (s == TW_EDEVICE)
             return s;
     }
     st = join_aux();
     if (st != TW_OK)
         return st;
+    // graphs the second context could not fit beside the batched search: once
+    // more here, now that the batch's memory is free
+    for (uint32_t t = 0; t < count; ++t) {
+        if (out_status[t] != TW_ENOMEM || graphs[t].n == 0)
+            continue;
+        GraphOutcome oc;
+        tw_status s = solve_one(c, graphs[t], rp ? &reds[t] : nullptr, lbs[t], k0s[t], &out_tw[t],
+                                out_orders + offs[t], rs, &oc);
+        out_status[t] = s;
+        outcomes[t] = oc;
+        if (s != TW_OK)
+            out_tw[t] = -1;
+        if (s == TW_EDEVICE)
+            return s;
+    }
     if (out_graph_stats)
         for (uint32_t t = 0; t < count; ++t) {
             tw_graph_stats &o = out_graph_stats[t];
@@ -1847,14 +2874,41 @@ tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t 
             o.start_k = outcomes[t].start_k;
             o.decisions = outcomes[t].decisions;
             o.path = outcomes[t].path;
+            o.peak_any = outcomes[t].peak_any;
         }
     add_stats(stats, rs, now_s() - t0);
     return TW_OK;
 }
 
+}  // namespace
+
+tw_status tw_solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t *out_tw,
+                         int32_t *out_orders, tw_status *out_status, tw_graph_stats *out_graph_stats,
+                         tw_stats *stats)
+{
+    return solve_batch(c, gs, count, out_tw, out_orders, out_status, out_graph_stats, stats, nullptr);
+}
+
+tw_status tw_trace_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, uint64_t first_arena_states,
+                         uint32_t max_records, tw_batch_level *out_records, uint32_t *out_nrecords,
+                         int32_t *out_tw, int32_t *out_orders, tw_status *out_status,
+                         tw_graph_stats *out_graph_stats)
+{
+    if (!c || (count && (!out_records || !out_nrecords)) || max_records == 0)
+        return TW_EINVAL;
+    for (uint32_t t = 0; t < count; ++t)
+        out_nrecords[t] = 0;
+    BatchTrace tr;
+    tr.max_records = max_records;
+    tr.first_arena = first_arena_states;
+    tr.records = out_records;
+    tr.nrecords = out_nrecords;
+    return solve_batch(c, gs, count, out_tw, out_orders, out_status, out_graph_stats, nullptr, &tr);
+}
+
 tw_status tw_probe_rate(int device, uint64_t bytes, uint64_t count, int mode, double *out_seconds)
 {
-    if (!out_seconds || mode < 0 || mode > 2 || bytes < 4096 || count == 0)
+    if (!out_seconds || mode < 0 || mode > 5 || bytes < 4096 || count == 0)
         return TW_EINVAL;
     *out_seconds = 0.0;
     if (hipSetDevice(device) != hipSuccess)

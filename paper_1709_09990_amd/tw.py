@@ -21,6 +21,7 @@ TW_K_ASCENDING, TW_K_LEARNED = 0, 1
 TW_REDUCE_NONE, TW_REDUCE_CLIQUE_PATHS = 0, 1
 TW_BATCH_ROUNDS, TW_BATCH_PERSISTENT = 0, 1
 TW_MMW_NONE, TW_MMW_PRUNE = 0, 1
+TW_CAPTURE_AUTO, TW_CAPTURE_OFF = 0, 1
 
 
 class TwError(RuntimeError):
@@ -52,6 +53,10 @@ class _Options(ctypes.Structure):
         ("batch_schedule", ctypes.c_int),
         ("reductions", ctypes.c_int),
         ("mmw_prune", ctypes.c_int),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("fault_inject_level", ctypes.c_int),
+        ("capture", ctypes.c_int),
     ]
 
 
@@ -92,6 +97,18 @@ class _GraphStats(ctypes.Structure):
         ("decisions", ctypes.c_uint32),
         ("path", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("peak_any", ctypes.c_uint64),
+    ]
+
+
+class _BatchLevel(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int32),
+        ("level", ctypes.c_int32),
+        ("count", ctypes.c_uint64),
+        ("successors", ctypes.c_uint64),
+        ("digest_sum", ctypes.c_uint64),
+        ("digest_xor", ctypes.c_uint64),
     ]
 
 
@@ -104,6 +121,8 @@ EXPORTS = (
     "tw_mpnn_param_count", "tw_mpnn_features", "tw_mpnn_create", "tw_mpnn_destroy",
     "tw_mpnn_set_params", "tw_mpnn_get_params", "tw_mpnn_predict", "tw_mpnn_gradients",
     "tw_mpnn_train_step", "tw_probe_rate", "tw_reductions", "tw_tree_decomposition",
+    "tw_trace_batch", "tw_mpnn_trace_floats", "tw_mpnn_trace",
+    "tw_decide128", "tw_solve128", "tw_trace_decide128", "tw_mmw128", "tw_order_width128",
 )
 
 _lib = None
@@ -128,6 +147,9 @@ def load():
                                  P(ctypes.c_int32), P(ctypes.c_int), P(_GraphStats), P(_Stats)]
     L.tw_trace_decide.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_int32, _SINK, ctypes.c_void_p,
                                   P(ctypes.c_int32)]
+    L.tw_trace_batch.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+                                 P(_BatchLevel), P(ctypes.c_uint32), P(ctypes.c_int32), P(ctypes.c_int32),
+                                 P(ctypes.c_int), P(_GraphStats)]
     L.tw_mmw.argtypes = [P(_Graph), P(ctypes.c_int32)]
     L.tw_order_width.argtypes = [P(_Graph), P(ctypes.c_int32), P(ctypes.c_int32)]
     L.tw_tree_decomposition.argtypes = [P(_Graph), P(ctypes.c_int32), P(ctypes.c_uint64), P(ctypes.c_int32),
@@ -150,15 +172,42 @@ def load():
     L.tw_mpnn_get_params.argtypes = [ctypes.c_void_p, f32p]
     L.tw_mpnn_predict.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_uint32, f32p]
     L.tw_mpnn_gradients.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_uint32, f32p, f32p, f32p]
+    L.tw_decide128.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_int32, P(ctypes.c_int32), P(_Stats)]
+    L.tw_solve128.argtypes = [ctypes.c_void_p, P(_Graph), P(ctypes.c_int32), P(ctypes.c_int32), P(_Stats)]
+    L.tw_trace_decide128.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_int32, _SINK, ctypes.c_void_p,
+                                     P(ctypes.c_int32)]
+    L.tw_mmw128.argtypes = [P(_Graph), P(ctypes.c_int32)]
+    L.tw_order_width128.argtypes = [P(_Graph), P(ctypes.c_int32), P(ctypes.c_int32)]
+    for name in ("tw_decide128", "tw_solve128", "tw_trace_decide128", "tw_mmw128", "tw_order_width128"):
+        getattr(L, name).restype = ctypes.c_int
+    L.tw_mpnn_trace_floats.argtypes = []
+    L.tw_mpnn_trace_floats.restype = ctypes.c_uint32
+    L.tw_mpnn_trace.argtypes = [ctypes.c_void_p, P(_Graph), f32p, f32p, f32p]
+    L.tw_mpnn_trace.restype = ctypes.c_int
     L.tw_mpnn_train_step.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_uint32, f32p, ctypes.c_float,
                                      ctypes.c_float, f32p]
     for name in ("tw_ctx_create", "tw_decide", "tw_solve", "tw_solve_batch", "tw_trace_decide",
                  "tw_mmw", "tw_order_width", "tw_mpnn_features", "tw_mpnn_create", "tw_mpnn_set_params",
                  "tw_mpnn_get_params", "tw_mpnn_predict", "tw_mpnn_gradients", "tw_mpnn_train_step",
-                 "tw_probe_rate", "tw_reductions", "tw_tree_decomposition"):
+                 "tw_probe_rate", "tw_reductions", "tw_tree_decomposition", "tw_trace_batch"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
+
+
+def _graph128(rows):
+    """A graph of up to 126 vertices from rows given as Python integers (or
+    anything int() accepts): two words per row, low then high."""
+    n = len(rows)
+    words = np.zeros(max(1, 2 * n), dtype=np.uint64)
+    for i, r in enumerate(rows):
+        r = int(r)
+        words[2 * i] = r & (2**64 - 1)
+        words[2 * i + 1] = (r >> 64) & (2**64 - 1)
+    g = _Graph()
+    g.n = n
+    g.adj = words.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    return g, words
 
 
 def _graph(rows):
@@ -254,7 +303,8 @@ class Context:
                  timing: bool = False, k_policy: int = TW_K_ASCENDING, weights_path: str | None = None,
                  batch_graph_states: int = 0, batch_chunk: int = 0, probe: int = 0, partition: int = 0,
                  reductions: int = TW_REDUCE_NONE, batch_schedule: int = TW_BATCH_ROUNDS,
-                 mmw_prune: int = TW_MMW_NONE):
+                 mmw_prune: int = TW_MMW_NONE, workspace: int = 0, workspace_bytes: int = 0,
+                 fault_inject_level: int = 0, capture: int = 0):
         L = load()
         self._L = L
         o = _Options()
@@ -276,6 +326,10 @@ class Context:
         o.reductions = reductions
         o.mmw_prune = mmw_prune
         o.batch_schedule = batch_schedule
+        o.workspace = ctypes.c_void_p(workspace) if workspace else None
+        o.workspace_bytes = workspace_bytes
+        o.fault_inject_level = fault_inject_level
+        o.capture = capture
         h = ctypes.c_void_p()
         st = L.tw_ctx_create(ctypes.byref(o), ctypes.byref(h))
         if st != TW_OK:
@@ -301,11 +355,16 @@ class Context:
             msg = self._L.tw_last_error(self._h).decode()
             raise TwError(st, msg or self._L.tw_status_str(st).decode())
 
-    def decide(self, rows, k: int):
+    def decide(self, rows, k: int, stats_on_error: dict | None = None):
+        """(yes, stats).  On an error the counters of the levels built go to
+        stats_on_error (when given) before TwError is raised."""
         g, keep = _graph(rows)
         yes = ctypes.c_int32(0)
         s = _Stats()
-        self._check(self._L.tw_decide(self._h, ctypes.byref(g), int(k), ctypes.byref(yes), ctypes.byref(s)))
+        st = self._L.tw_decide(self._h, ctypes.byref(g), int(k), ctypes.byref(yes), ctypes.byref(s))
+        if st != TW_OK and stats_on_error is not None:
+            stats_on_error.update(_stats_dict(s))
+        self._check(st)
         return bool(yes.value), _stats_dict(s)
 
     def solve(self, rows):
@@ -316,6 +375,41 @@ class Context:
         self._check(self._L.tw_solve(self._h, ctypes.byref(g), ctypes.byref(tw),
                                      order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(s)))
         return tw.value, order, _stats_dict(s)
+
+    def decide128(self, rows, k: int):
+        """decide(k) for a graph of up to 126 vertices (rows as Python ints)."""
+        g, keep = _graph128(rows)
+        yes = ctypes.c_int32(0)
+        s = _Stats()
+        self._check(self._L.tw_decide128(self._h, ctypes.byref(g), int(k), ctypes.byref(yes), ctypes.byref(s)))
+        return bool(yes.value), _stats_dict(s)
+
+    def solve128(self, rows):
+        g, keep = _graph128(rows)
+        tw = ctypes.c_int32(0)
+        order = np.zeros(max(1, len(rows)), dtype=np.int32)
+        s = _Stats()
+        self._check(self._L.tw_solve128(self._h, ctypes.byref(g), ctypes.byref(tw),
+                                        order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(s)))
+        return tw.value, order[:len(rows)], _stats_dict(s)
+
+    def trace_decide128(self, rows, k: int):
+        """decide(k) for a graph of up to 126 vertices with every level:
+        (level, count, expansions, successors, states) where states is a
+        (count, 2) uint64 array of (low, high) words in the order found."""
+        g, keep = _graph128(rows)
+        levels = []
+
+        def sink(rec_p, user):
+            r = rec_p.contents
+            c = int(r.count)
+            w = np.ctypeslib.as_array(r.states, shape=(2 * c,)).copy() if c else np.zeros(0, np.uint64)
+            levels.append((r.level, c, int(r.expansions), int(r.successors), w.reshape(c, 2)))
+
+        cb = _SINK(sink)
+        yes = ctypes.c_int32(0)
+        self._check(self._L.tw_trace_decide128(self._h, ctypes.byref(g), int(k), cb, None, ctypes.byref(yes)))
+        return bool(yes.value), levels
 
     def solve_batch(self, graphs, graph_stats: bool = False):
         """tw, orders, statuses, stats (and per-graph stats dicts if asked)."""
@@ -344,6 +438,47 @@ class Context:
                    for t in range(cnt)]
             return res + (per,)
         return res
+
+    def trace_batch(self, graphs, max_records: int = 4096, first_arena_states: int = 0):
+        """tw_solve_batch with per-level records of the batched graphs:
+        (tws, orders, statuses, per-graph stats dicts, records) where
+        records[t] is a list of (k, level, count, successors, digest_sum,
+        digest_xor) tuples in the order the levels were built (empty for
+        graphs solved off the batch)."""
+        arrs = [np.ascontiguousarray(np.asarray(r, dtype=np.uint64)) for r in graphs]
+        cnt = len(arrs)
+        gs = (_Graph * max(1, cnt))()
+        for t, a in enumerate(arrs):
+            gs[t].n = len(a)
+            gs[t].adj = a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        tws = np.zeros(max(1, cnt), dtype=np.int32)
+        orders = np.zeros(max(1, sum(len(a) for a in arrs)), dtype=np.int32)
+        status = np.zeros(max(1, cnt), dtype=np.int32)
+        gst = (_GraphStats * max(1, cnt))()
+        recs = (_BatchLevel * (max(1, cnt) * int(max_records)))()
+        nrec = np.zeros(max(1, cnt), dtype=np.uint32)
+        self._check(self._L.tw_trace_batch(
+            self._h, gs, cnt, int(first_arena_states), int(max_records), recs,
+            nrec.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+            tws.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), gst))
+        out_orders, off = [], 0
+        for a in arrs:
+            out_orders.append(orders[off:off + len(a)].copy())
+            off += len(a)
+        per = [{name: getattr(gst[t], name) for name, _ in _GraphStats._fields_ if name != "reserved"}
+               for t in range(cnt)]
+        records = []
+        for t in range(cnt):
+            m = min(int(nrec[t]), int(max_records))
+            if int(nrec[t]) > int(max_records):
+                raise RuntimeError(f"graph {t}: {int(nrec[t])} levels recorded, above max_records")
+            base = t * int(max_records)
+            records.append([(recs[base + j].k, recs[base + j].level, int(recs[base + j].count),
+                             int(recs[base + j].successors), int(recs[base + j].digest_sum),
+                             int(recs[base + j].digest_xor)) for j in range(m)])
+        return tws[:cnt].copy(), out_orders, status[:cnt].copy(), per, records
 
     def trace_decide(self, rows, k: int):
         """decide(k) returning every level (states unordered) as Level records."""
@@ -444,6 +579,34 @@ class Mpnn:
                                               ctypes.byref(loss), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
         return loss.value, g
 
+    def trace(self, rows, target):
+        """One graph's forward and backward pass with the kernels' float32
+        intermediates (tw_mpnn_trace): a dict of 64 x 64 arrays per quantity
+        (M, Z, dZ: lists over layers 0..2; P, dH: dicts for layers 1, 2; dH3),
+        r [128], y [2], and the gradient vector."""
+        gs, keep = _graph_array([rows])
+        t = np.ascontiguousarray(target, dtype=np.float32)
+        nf = int(self._L.tw_mpnn_trace_floats())
+        tr = np.zeros(nf, dtype=np.float32)
+        g = np.zeros(mpnn_param_count(), dtype=np.float32)
+        self._check(self._L.tw_mpnn_trace(self._h, gs, t.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                          tr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                          g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        blk = 4096
+
+        def m(off):
+            return tr[off:off + blk].reshape(64, 64).astype(np.float64)
+        r0 = 6 * blk
+        dh3 = r0 + 256
+        dz = dh3 + blk
+        pp = dz + 3 * blk
+        dh = pp + 2 * blk
+        out = {"M": [m(l * blk) for l in range(3)], "Z": [m(3 * blk + l * blk) for l in range(3)],
+               "r": tr[r0:r0 + 128].astype(np.float64), "y": tr[r0 + 128:r0 + 130].astype(np.float64),
+               "dH3": m(dh3), "dZ": [m(dz + l * blk) for l in range(3)],
+               "P": {l: m(pp + (l - 1) * blk) for l in (1, 2)}, "dH": {l: m(dh + (l - 1) * blk) for l in (1, 2)}}
+        return out, g
+
     def train_step(self, graphs, targets, lr: float, weight_decay: float = 0.0) -> float:
         gs, keep = _graph_array(graphs)
         t = np.ascontiguousarray(targets, dtype=np.float32)
@@ -473,3 +636,12 @@ def read_weights(path: str) -> np.ndarray:
             raise ValueError("not a network parameter file")
         count = int(np.frombuffer(f.read(4), dtype="<u4")[0])
         return np.frombuffer(f.read(4 * count), dtype="<f4").copy()
+
+
+def mmw128(rows) -> int:
+    g, keep = _graph128(rows)
+    lb = ctypes.c_int32(0)
+    st = load().tw_mmw128(ctypes.byref(g), ctypes.byref(lb))
+    if st != TW_OK:
+        raise TwError(st, "tw_mmw128")
+    return lb.value

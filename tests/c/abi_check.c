@@ -14,6 +14,11 @@ int main(void)
     printf("off_mmw_prune %zu\n", offsetof(tw_options, mmw_prune));
     printf("off_batch_schedule %zu\n", offsetof(tw_options, batch_schedule));
     printf("off_batch_chunk %zu\n", offsetof(tw_options, batch_chunk));
+    printf("off_workspace %zu\n", offsetof(tw_options, workspace));
+    printf("off_workspace_bytes %zu\n", offsetof(tw_options, workspace_bytes));
+    printf("off_fault_inject_level %zu\n", offsetof(tw_options, fault_inject_level));
+    printf("off_capture %zu\n", offsetof(tw_options, capture));
+    printf("sizeof_batch_level %zu\n", sizeof(tw_batch_level));
     printf("sizeof_stats %zu\n", sizeof(tw_stats));
     printf("sizeof_graph_stats %zu\n", sizeof(tw_graph_stats));
     printf("sizeof_graph %zu\n", sizeof(tw_graph));

@@ -37,12 +37,14 @@ def c_program(tmp_path_factory):
 def test_struct_layouts_match_binding(c_program):
     f = c_program
     assert int(f["sizeof_options"][0]) == ctypes.sizeof(T._Options)
-    for name in ("mmw_prune", "reductions", "batch_schedule", "batch_chunk"):
+    for name in ("mmw_prune", "reductions", "batch_schedule", "batch_chunk", "workspace", "workspace_bytes",
+                 "fault_inject_level", "capture"):
         assert int(f["off_" + name][0]) == getattr(T._Options, name).offset, name
     assert int(f["sizeof_stats"][0]) == ctypes.sizeof(T._Stats)
     assert int(f["sizeof_graph_stats"][0]) == ctypes.sizeof(T._GraphStats)
     assert int(f["sizeof_level_record"][0]) == ctypes.sizeof(T._LevelRecord)
     assert int(f["sizeof_graph"][0]) == ctypes.sizeof(T._Graph)
+    assert int(f["sizeof_batch_level"][0]) == ctypes.sizeof(T._BatchLevel)
 
 
 def test_host_entry_points_from_c(c_program):

@@ -241,6 +241,35 @@ def test_set_hashes_order_independent(oracle):
     assert oracle.set_hashes(np.zeros(0, dtype=np.uint64)) == (0, 0, 0)
 
 
+def test_set_hashes_pinned(oracle):
+    """The level digests: the sum uses splitmix64's output function (its
+    published sequence from seed 0 starts 0xe220a8397b1dcdaf,
+    0x6e789e6aa1b965f4: the output function of the state after one and two
+    increments of 0x9e3779b97f4a7c15); both digests add over disjoint unions;
+    dropping, duplicating or replacing one state changes them."""
+    gamma = 0x9E3779B97F4A7C15
+    x = np.array([gamma, (2 * gamma) % 2**64], dtype=np.uint64)
+    assert [int(v) for v in oracle._mix_a(x)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4]
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        a = np.unique(rng.integers(0, 2**62, size=int(rng.integers(2, 2000)), dtype=np.uint64))
+        b = np.unique(rng.integers(2**62, 2**63, size=int(rng.integers(1, 2000)), dtype=np.uint64))
+        ca, sa, xa = oracle.set_hashes(a)
+        cb, sb, xb = oracle.set_hashes(b)
+        assert oracle.set_hashes(np.concatenate([a, b])) == (ca + cb, (sa + sb) % 2**64, xa ^ xb)
+        full = oracle.set_hashes(a)
+        dropped = oracle.set_hashes(a[1:])
+        dup = oracle.set_hashes(np.concatenate([a, a[:1]]))
+        repl = a.copy()
+        repl[0] = np.uint64(2**63 + 7)
+        replaced = oracle.set_hashes(repl)
+        for other in (dropped, dup, replaced):
+            assert other[1] != full[1] and other[2] != full[2] or other[0] != full[0]
+        assert replaced[0] == full[0] and replaced[1] != full[1] and replaced[2] != full[2]
+        # a duplicated state leaves the xor digest unchanged but not the sum or the count
+        assert dup[1] != full[1] and dup[0] == full[0] + 1
+
+
 def test_pins_catch_planted_mistakes(oracle):
     """Mistakes planted in a copy of the oracle's Q (on the CPU) are caught by
     the pins above: counting v itself, or dropping the 'through S only' rule."""
