@@ -248,7 +248,7 @@ def _outcomes(graphs, tws, status, per) -> dict:
 
 
 def batch_config_leg(graphs, label: str, max_states: int, weights: str, reductions: bool,
-                     ceiling: bool = False) -> dict:
+                     ceiling: bool = False, per_call: int = 128) -> dict:
     """Graphs solved per second, plain ascending bounds against the learned
     start bound, on one batch, each graph's levels capped at max_states
     states (a graph whose level would exceed the cap returns TW_ECAPACITY with
@@ -256,7 +256,8 @@ def batch_config_leg(graphs, label: str, max_states: int, weights: str, reductio
     batch's graphs of n <= 32).  Answers must agree on every graph both
     policies solve.  With ceiling: the certifying work alone (decide(tw) and,
     when tw is above the lower bound, decide(tw - 1)) per solved graph, i.e.
-    a start bound that is never wrong."""
+    a start bound that is never wrong.  The graphs go in calls of per_call
+    (one progress line each); the time is the sum over the calls."""
     import numpy as np
     from paper_1709_09990_amd import autotune
     from paper_1709_09990_amd import tw as T
@@ -270,20 +271,30 @@ def batch_config_leg(graphs, label: str, max_states: int, weights: str, reductio
            "max_states_per_level": max_states, "reductions": reductions, "tuned_options": tuned,
            "weights": os.path.relpath(weights, ROOT)}
     res = {}
+    out["graphs_per_call"] = per_call
     for name, kw in (("plain", {}), ("learned", {"k_policy": T.TW_K_LEARNED, "weights_path": weights})):
+        tws, status, per = [], [], []
+        exp = dec = 0
+        dt = 0.0
         with T.Context(device=0, **base, **kw) as c:
-            t0 = time.perf_counter()
-            tws, _, status, st, per = c.solve_batch(graphs, graph_stats=True)
-            dt = time.perf_counter() - t0
+            for lo in range(0, len(graphs), per_call):
+                t0 = time.perf_counter()
+                a, _, b, st, d = c.solve_batch(graphs[lo:lo + per_call], graph_stats=True)
+                dt += time.perf_counter() - t0
+                tws += [int(x) for x in a]
+                status += [int(x) for x in b]
+                per += d
+                exp += st["expansions"]
+                dec += st["decisions"]
+                print(json.dumps({"leg": label, "policy": name, "graphs_done": lo + len(a),
+                                  "seconds": round(dt, 1)}), flush=True)
         res[name] = (tws, status, per)
         o = _outcomes(graphs, tws, status, per)
         o["seconds"] = round(dt, 2)
         o["graphs_solved_per_s"] = round(o["solved"] / dt, 2)
-        o["expansions"] = st["expansions"]
-        o["bounds_tried"] = st["decisions"]
+        o["expansions"] = exp
+        o["bounds_tried"] = dec
         out[name] = o
-        print(json.dumps({"leg": label, "policy": name, "seconds": round(dt, 1), "solved": o["solved"]}),
-              flush=True)
     tp, sp, _ = res["plain"]
     tl, sl, _ = res["learned"]
     both = [t for t in range(len(graphs)) if sp[t] == 0 and sl[t] == 0]
@@ -298,7 +309,9 @@ def batch_config_leg(graphs, label: str, max_states: int, weights: str, reductio
         with T.Context(device=0, max_states=max_states, **{k: v for k, v in kw.items()
                                                            if k in ("reductions", "load_factor", "probe")}) as c:
             t0 = time.perf_counter()
-            for t in both:
+            for q, t in enumerate(both):
+                if q % 256 == 255:
+                    print(json.dumps({"leg": label, "ceiling_graphs_done": q + 1}), flush=True)
                 lb = T.mmw(graphs[t])
                 if reductions:
                     lb = max(lb, len(T.reductions(graphs[t])[0]) - 1)

@@ -22,10 +22,27 @@ def _levels(ctx, rows, k):
     return yes, [(lv.level, lv.count, lv.successors, np.sort(lv.states).tobytes()) for lv in levels]
 
 
+class _DeviceRange:
+    """A caller-owned device buffer from the HIP runtime the library uses
+    (hipMalloc / hipFree through ctypes)."""
+
+    def __init__(self, nbytes):
+        import ctypes
+        from paper_1709_09990_amd import tw as T
+        T.load()
+        self._hip = ctypes.CDLL("libamdhip64.so.7", mode=ctypes.RTLD_GLOBAL)
+        self.ptr = ctypes.c_void_p()
+        assert self._hip.hipMalloc(ctypes.byref(self.ptr), ctypes.c_size_t(nbytes)) == 0
+
+    def free(self):
+        if self.ptr:
+            self._hip.hipFree(self.ptr)
+            self.ptr = None
+
+
 def _device_range(nbytes):
-    import torch
-    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
-    return buf, buf.data_ptr()
+    r = _DeviceRange(nbytes)
+    return r, r.ptr.value
 
 
 def test_workspace_levels_equal_own_memory(oracle):
@@ -43,7 +60,7 @@ def test_workspace_levels_equal_own_memory(oracle):
             tw_own, _, _ = own.solve(rows)
             assert tw_ws == tw_own == k
             assert oracle.order_width(rows, order_ws) == k
-    del buf
+    buf.free()
 
 
 def test_workspace_batch_and_too_small(oracle):
@@ -67,7 +84,8 @@ def test_workspace_batch_and_too_small(oracle):
         # the context stays usable for what fits
         yes, _ = tiny.decide(G.path(12), 1)
         assert yes
-    del buf, small
+    buf.free()
+    small.free()
 
 
 @pytest.mark.parametrize("level", [1, 4, 9])
