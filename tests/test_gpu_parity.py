@@ -397,10 +397,10 @@ def test_partitioned_insert_levels_match(oracle, maker):
 def test_probe_rate_reference():
     """The random-access reference kernel runs in every mode and rejects bad arguments."""
     from paper_1709_09990_amd import tw as T
-    for mode in (0, 1, 2):
+    for mode in range(6):
         r = T.probe_rate(64 << 20, 1 << 22, mode)
         assert math.isfinite(r) and r > 1e6, (mode, r)
-    for bad in ((64 << 20, 1 << 22, 3), (1024, 1 << 22, 0), (64 << 20, 0, 0)):
+    for bad in ((64 << 20, 1 << 22, 6), (64 << 20, 1 << 22, -1), (1024, 1 << 22, 0), (64 << 20, 0, 0)):
         with pytest.raises(T.TwError):
             T.probe_rate(*bad)
 
