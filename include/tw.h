@@ -192,6 +192,18 @@ tw_status tw_decide(tw_ctx *ctx, const tw_graph *g, int32_t k, int32_t *out_yes,
  * *out_tw before returning. */
 tw_status tw_solve(tw_ctx *ctx, const tw_graph *g, int32_t *out_tw, int32_t *out_order, tw_stats *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): tw_solve with
+ * ascending bounds from the minor-min-width lower bound (options.k_policy is
+ * ignored), where every device buffer of the call (levels, hash table,
+ * counters) lies in the library's static scratch of 64 MiB per GPU instead
+ * of memory the call allocates.  The call makes no hipMalloc or hipFree.
+ * n must be at most 32 (else TW_EINVAL); a search whose levels do not fit
+ * the scratch fails with TW_ECAPACITY.  Every call on one GPU shares that
+ * GPU's scratch, which keeps the last call's contents: calls that overlap on
+ * one GPU (from several threads or contexts) race and must not be made. */
+tw_status tw_solve_noalloc(tw_ctx *ctx, const tw_graph *g, int32_t *out_tw, int32_t *out_order, tw_stats *stats);
+
 /* tw_solve for count graphs of uneven size.  out_tw[count], out_status[count];
  * out_orders holds the orders back to back (sum of n entries, graph order).
  * Graphs with n <= 48 are solved together on the device, each with its own

@@ -30,9 +30,9 @@ namespace {
 
 using twk::LevelCounters;
 
-// First-fit allocator over one caller-given device range (options.workspace):
-// host bookkeeping only, blocks of 256-byte multiples, neighbours merged on
-// release.
+// First-fit allocator over one caller-given device range (options.workspace,
+// or the static scratch of tw_solve_noalloc): host bookkeeping only, blocks of
+// 256-byte multiples, neighbours merged on release.
 struct Carver {
     uintptr_t base = 0;
     size_t bytes = 0;
@@ -108,6 +108,37 @@ struct Graph {
     int n = 0;
     uint64_t rows[64] = {};
 };
+
+}  // namespace
+
+// Device memory of tw_solve_noalloc: one array per GPU, held until the process
+// ends.  Host code never passes `scratch` itself to a kernel (on the host the
+// name is a stand-in, not a device address): the address of each device's
+// copy is looked up once per device with hipGetSymbolAddress and kept in
+// g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kNoAllocMaxN = 32;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::atomic<void *> g_scratch_ptr[kMaxDevices];
+
+// With device `device` current: the address of its copy of `scratch`.
+hipError_t scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    if (g_scratch_ptr[device].load())
+        return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    g_scratch_ptr[device].store(ptr);
+    return hipSuccess;
+}
 
 }  // namespace
 
@@ -2374,6 +2405,10 @@ tw_status tw_ctx_create(const tw_options *options, tw_ctx **out)
             return bad(e);
         c->own_stream = true;
     }
+    if (scratch_setup(c->device) != hipSuccess) {
+        tw_ctx_destroy(c);
+        return TW_EDEVICE;
+    }
     if (hipHostMalloc((void **)&c->h_ctr, sizeof(LevelCounters), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->h_find, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
         tw_ctx_destroy(c);
@@ -2641,6 +2676,68 @@ tw_status tw_order_width128(const tw_graph128 *gr, const int32_t *order, int32_t
     if (s != TW_OK)
         return s;
     *out_width = fill_in_width_wide(g, order);
+    return TW_OK;
+}
+
+tw_status tw_solve_noalloc(tw_ctx *c, const tw_graph *gr, int32_t *out_tw, int32_t *out_order, tw_stats *stats)
+{
+    if (!c || !out_tw || !out_order)
+        return TW_EINVAL;
+    c->err.clear();
+    Graph g;
+    tw_status s = validate(c, gr, g);
+    if (s != TW_OK)
+        return s;
+    if (g.n > kNoAllocMaxN)
+        return fail(c, TW_EINVAL, "tw_solve_noalloc takes n <= %d (n=%d)", kNoAllocMaxN, g.n);
+    if (hipSetDevice(c->device) != hipSuccess)
+        return fail(c, TW_EDEVICE, "hipSetDevice failed");
+    void *base = c->device >= 0 && c->device < kMaxDevices ? g_scratch_ptr[c->device].load() : nullptr;
+    if (!base)
+        return fail(c, TW_EDEVICE, "static scratch of device %d not set up", c->device);
+    const double t0 = now_s();
+    RunStats rs;
+    int lb = mmw_bound(g);
+    Reduction red;
+    if (c->opt.reductions) {
+        red = reduction_of(g, lb);
+        lb = std::max(lb, red.clique_size - 1);
+    }
+    // every device buffer of this call comes from the scratch: the context's
+    // own buffers and cache are set aside and put back afterwards
+    Carver scr;
+    scr.reset(base, kScratchBytes);
+    Buf saved_adj = c->d_adj, saved_ctr = c->d_ctr, saved_find = c->d_find, saved_table = c->table,
+        saved_bloom = c->bloom, saved_parts = c->parts, saved_meta = c->part_meta;
+    std::vector<Buf> saved_cache;
+    saved_cache.swap(c->cache);
+    Carver *saved_carve = c->carve;
+    const uint64_t saved_budget = c->keep_budget;
+    c->d_adj = c->d_ctr = c->d_find = c->table = c->bloom = c->parts = c->part_meta = Buf{};
+    c->carve = &scr;
+    c->keep_budget = kScratchBytes / 4;
+    c->no_capture = true;
+    s = ensure_ctx_buffers(c);
+    if (s == TW_OK)
+        s = solve_one(c, g, c->opt.reductions ? &red : nullptr, lb, lb, out_tw, out_order, rs, nullptr);
+    if (s == TW_ENOMEM)
+        s = fail(c, TW_ECAPACITY, "the search needs more than the %zu-byte static scratch (%s)", kScratchBytes,
+                 c->err.c_str());
+    // the carved buffers are dropped with the scratch's bookkeeping
+    c->d_adj = saved_adj;
+    c->d_ctr = saved_ctr;
+    c->d_find = saved_find;
+    c->table = saved_table;
+    c->bloom = saved_bloom;
+    c->parts = saved_parts;
+    c->part_meta = saved_meta;
+    c->cache.swap(saved_cache);
+    c->carve = saved_carve;
+    c->keep_budget = saved_budget;
+    c->no_capture = false;
+    if (s != TW_OK)
+        return s;
+    add_stats(stats, rs, now_s() - t0);
     return TW_OK;
 }
 

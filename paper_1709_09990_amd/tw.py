@@ -121,7 +121,7 @@ EXPORTS = (
     "tw_mpnn_param_count", "tw_mpnn_features", "tw_mpnn_create", "tw_mpnn_destroy",
     "tw_mpnn_set_params", "tw_mpnn_get_params", "tw_mpnn_predict", "tw_mpnn_gradients",
     "tw_mpnn_train_step", "tw_probe_rate", "tw_reductions", "tw_tree_decomposition",
-    "tw_trace_batch", "tw_mpnn_trace_floats", "tw_mpnn_trace",
+    "tw_trace_batch", "tw_solve_noalloc", "tw_mpnn_trace_floats", "tw_mpnn_trace",
     "tw_decide128", "tw_solve128", "tw_trace_decide128", "tw_mmw128", "tw_order_width128",
 )
 
@@ -143,6 +143,7 @@ def load():
     L.tw_ctx_destroy.restype = None
     L.tw_decide.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_int32, P(ctypes.c_int32), P(_Stats)]
     L.tw_solve.argtypes = [ctypes.c_void_p, P(_Graph), P(ctypes.c_int32), P(ctypes.c_int32), P(_Stats)]
+    L.tw_solve_noalloc.argtypes = [ctypes.c_void_p, P(_Graph), P(ctypes.c_int32), P(ctypes.c_int32), P(_Stats)]
     L.tw_solve_batch.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_uint32, P(ctypes.c_int32),
                                  P(ctypes.c_int32), P(ctypes.c_int), P(_GraphStats), P(_Stats)]
     L.tw_trace_decide.argtypes = [ctypes.c_void_p, P(_Graph), ctypes.c_int32, _SINK, ctypes.c_void_p,
@@ -189,7 +190,8 @@ def load():
     for name in ("tw_ctx_create", "tw_decide", "tw_solve", "tw_solve_batch", "tw_trace_decide",
                  "tw_mmw", "tw_order_width", "tw_mpnn_features", "tw_mpnn_create", "tw_mpnn_set_params",
                  "tw_mpnn_get_params", "tw_mpnn_predict", "tw_mpnn_gradients", "tw_mpnn_train_step",
-                 "tw_probe_rate", "tw_reductions", "tw_tree_decomposition", "tw_trace_batch"):
+                 "tw_probe_rate", "tw_reductions", "tw_tree_decomposition", "tw_trace_batch",
+                 "tw_solve_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -410,6 +412,18 @@ class Context:
         yes = ctypes.c_int32(0)
         self._check(self._L.tw_trace_decide128(self._h, ctypes.byref(g), int(k), cb, None, ctypes.byref(yes)))
         return bool(yes.value), levels
+
+    def solve_noalloc(self, rows):
+        """tw_solve_noalloc: as solve, with every device buffer of the call in
+        the library's static scratch (ascending bounds; n <= 32)."""
+        g, keep = _graph(rows)
+        tw = ctypes.c_int32(0)
+        order = np.zeros(len(keep), dtype=np.int32)
+        s = _Stats()
+        self._check(self._L.tw_solve_noalloc(self._h, ctypes.byref(g), ctypes.byref(tw),
+                                             order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                             ctypes.byref(s)))
+        return tw.value, order, _stats_dict(s)
 
     def solve_batch(self, graphs, graph_stats: bool = False):
         """tw, orders, statuses, stats (and per-graph stats dicts if asked)."""
