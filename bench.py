@@ -476,6 +476,7 @@ def main():
     ap.add_argument("--cap", type=int, default=1 << 26, help="states per level for the two legs above")
     ap.add_argument("--reduce-batches", action="store_true", help="run the two legs above with the section 3.1 reductions")
     ap.add_argument("--large-n64", action="store_true", help="add the n=64 partial 12-tree leg (exact vs Bloom, capped levels)")
+    ap.add_argument("--large-cap-log2", type=int, default=29, help="log2 of the states-per-level cap of that leg")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -588,7 +589,7 @@ def main():
     if not args.no_batch:
         out["batch"] = batch_leg()
     if args.large_n64:
-        out["large_n64"] = large_leg()
+        out["large_n64"] = large_leg(args.large_cap_log2)
     if args.batch_n16_48 or args.learned_n20_56:
         from paper_1709_09990_amd import graphs as G
         wts = WEIGHTS_N40_REDUCED if args.reduce_batches else WEIGHTS

@@ -138,8 +138,8 @@ typedef struct {
                                  the batched search the graph reaching that level leaves the batch
                                  for the single-graph path.  Answers and levels are unchanged; with
                                  max_states at that level's size the replay fails with TW_ECAPACITY */
-    int capture;              /* TW_CAPTURE_AUTO (default): tw_solve (and tw_solve_batch's single-graph
-                                 path) runs a bound's whole level loop (Listing 1, §3.1) as one replay of
+    int capture;              /* TW_CAPTURE_AUTO (default): tw_decide, tw_solve (and tw_solve_batch's
+                                 single-graph path) run a bound's whole level loop (Listing 1, §3.1) as one replay of
                                  a HIP graph when every level fits its binomial bound C(m, i) within
                                  256 MiB (n <= 25 or so; exact dedup, no MMW pruning, no test hooks): the
                                  launches read each level's size and the bound from device memory and do

@@ -2502,7 +2502,23 @@ tw_status tw_decide(tw_ctx *c, const tw_graph *gr, int32_t k, int32_t *out_yes, 
     Reduction red;
     if (c->opt.reductions)
         red = reduction_of(g, -1);
-    s = decide_checked(c, g, c->opt.reductions ? &red : nullptr, k, kKeepPair, levels, &yes, rs);
+    s = kNotCaptured;
+    if (Captured *cap = capture_for(c, g)) {
+        // the level loop as one graph replay (NO without a search below the clique bound)
+        if (c->opt.reductions && k < red.clique_size - 1) {
+            rs.decisions++;
+            s = TW_OK;
+        } else {
+            s = captured_decide(c, *cap, c->opt.reductions ? augmented(g, red, k) : g, k,
+                                c->opt.reductions ? ~red.clique : ~0ull, &yes, rs);
+        }
+        if (s == kNotCaptured) {
+            rs = RunStats{};
+            c->err.clear();
+        }
+    }
+    if (s == kNotCaptured)
+        s = decide_checked(c, g, c->opt.reductions ? &red : nullptr, k, kKeepPair, levels, &yes, rs);
     free_levels(c, levels);
     add_stats(stats, rs, now_s() - t0);  // the work done, also when the call fails
     if (s != TW_OK)

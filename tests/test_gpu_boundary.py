@@ -142,3 +142,18 @@ def test_fault_inject_batch_falls_back(oracle):
     # every graph whose bounds reach level 3 went to the single-graph path
     assert sum(1 for p in per if p["path"] == 1) >= 20
     assert st["retries"] >= 1
+
+
+def test_batch_memory_shortfall_falls_back(oracle):
+    """Batch arenas too large for the device (2^35 states per graph): the
+    batched launch cannot get its memory, and its graphs are solved on the
+    single-graph path instead of failing the call; every answer is returned."""
+    from paper_1709_09990_amd import tw as T
+    graphs = G.workload_batch(12, seed0=55000, n_lo=12, n_hi=22)
+    want = [oracle.treewidth_bfs(r, oracle.mmw(r)) for r in graphs]
+    with T.Context(device=0, batch_graph_states=1 << 35) as c:
+        tws, orders, status, _, per = c.solve_batch(graphs, graph_stats=True)
+    assert list(status) == [0] * len(graphs) and list(tws) == want
+    assert all(p["path"] in (1, 2) for p in per)
+    for rows, tw, order in zip(graphs, tws, orders):
+        assert oracle.order_width(rows, order) == tw

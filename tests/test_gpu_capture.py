@@ -21,8 +21,12 @@ def _pairs(graphs, cap_kw, off_kw, oracle):
             tw_a, order_a, st_a = cap.solve(rows)
             # eager work of the program between replays
             tw_b, order_b, st_b = off.solve(rows)
-            yes, _ = cap.decide(rows, max(0, tw_b - 1))
-            assert yes == (tw_b == 0)
+            for k in {max(0, tw_b - 1), tw_b}:
+                yes_a, sd_a = cap.decide(rows, k)
+                yes_b, sd_b = off.decide(rows, k)
+                assert yes_a == yes_b == (k >= tw_b)
+                for key in KEYS:
+                    assert sd_a[key] == sd_b[key], (key, k)
             assert tw_a == tw_b
             assert oracle.order_width(rows, order_a) == tw_a
             for key in KEYS:
