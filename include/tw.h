@@ -61,7 +61,10 @@ enum {
 /* Choice of the bounds k tried by tw_solve / tw_solve_batch (§3.1). */
 enum {
     TW_K_ASCENDING = 0, /* k = minor-min-width lower bound (§3.3), then k+1, ... until YES */
-    TW_K_LEARNED = 1    /* start from a predicted k; YES at t is certified by NO at t-1 or t = lower bound */
+    TW_K_LEARNED = 1    /* start from a predicted k; YES at t is certified by NO at t-1 or t = lower bound; a
+                           graph whose predicted largest level exceeds half of what fits (max_states, else
+                           device memory), or with more than 40 vertices (beyond the sizes the networks were
+                           trained on), starts at the lower bound */
 };
 
 /* A graph: n rows, host pointer, caller-owned. */

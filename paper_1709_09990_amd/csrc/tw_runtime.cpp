@@ -2292,11 +2292,18 @@ bool read_weights(const char *path, std::vector<float> &params)
 //  - Start bound: one below the prediction rounded down, clamped to [lb, n-2].
 //    Starting at tw-1 costs nothing extra (the NO at tw-1 certifies the answer
 //    anyway), while starting above tw adds a YES run at a larger bound, the
-//    most expensive kind; so errors are pushed downwards.
+//    most expensive kind (and one whose levels may not fit); so errors are
+//    pushed downwards.
+//  - Graphs larger than any the network was trained on (kLearnedMaxN) keep
+//    the ascending search's start and arena: predictions there overshoot.
 //  - Admission: the arena of a batched graph is 16 x the predicted peak level
 //    (never below the default); a graph whose arena would exceed kArenaMax is
-//    sent to the single-graph path at once instead of overflowing in the batch.
+//    sent to the single-graph path at once (where it runs beside the batch, on
+//    a second stream) instead of overflowing in the batch.
 constexpr uint64_t kArenaMax = 1ull << 23;
+// largest graphs whose learned start is used (the committed networks were
+// trained on graphs of 16..30 and 16..40 vertices)
+constexpr int kLearnedMaxN = 40;
 // arena of the second batched attempt for graphs that outgrew the first
 constexpr uint64_t kArenaRetry = 1ull << 24;
 
@@ -2315,14 +2322,23 @@ tw_status predict_starts(tw_ctx *c, const std::vector<Graph> &graphs, const std:
     tw_status s = tw_mpnn_predict(c->net, gs.data(), (uint32_t)ids.size(), pred.data());
     if (s != TW_OK)
         return fail(c, s, "network prediction failed");
+    // states a level may hold: the cap, else what a table and two levels of
+    // 8-byte keys at load 0.5 leave of the device memory (about 34 bytes each)
+    const double fit = c->opt.max_states ? (double)c->opt.max_states : (double)free_device_bytes(c) / 34.0;
     for (size_t q = 0; q < ids.size(); ++q) {
         const int t = ids[q];
         const int n = graphs[(size_t)t].n;
+        if (n > kLearnedMaxN)
+            continue;  // beyond the trained sizes: the ascending search's start and arena
         const double tw_pred = (double)pred[2 * q] * n;
+        const double peak = std::exp2(std::min(40.0, std::max(0.0, 32.0 * (double)pred[2 * q + 1]))) - 1.0;
         int k0 = (int)std::floor(tw_pred) - 1;
         k0 = std::max(lbs[(size_t)t], std::min(k0, n - 2));
+        // a start above the ascending frontier pays off only when its levels
+        // fit: a predicted peak beyond half of what fits starts at the frontier
+        if (peak > 0.5 * fit)
+            k0 = lbs[(size_t)t];
         k0s[(size_t)t] = k0;
-        const double peak = std::exp2(std::min(40.0, std::max(0.0, 32.0 * (double)pred[2 * q + 1]))) - 1.0;
         const double want = 16.0 * peak;
         if (too_big && want > (double)kArenaMax)
             (*too_big)[(size_t)t] = 1;

@@ -12,3 +12,13 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_cpu_baseline_fields():
+    """The oracle leg of the bench line (CPU only): a bounded sample, its
+    rate, and the cores it used."""
+    sys.path.insert(0, ROOT)
+    import bench
+    r = bench.cpu_baseline(0.3, threads=1)
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["unit"] == "expansions/s"
+    assert r["value"] > 0 and "partial 8-tree" in r["sample"]
