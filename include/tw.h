@@ -102,7 +102,8 @@ typedef struct {
     uint64_t batch_graph_states; /* arena states per graph (0 = as many as half the free device memory
                                     allows, 2^16..2^22); a graph that outgrows its arena or table is
                                     re-solved alone by the tw_solve path */
-    uint32_t batch_chunk;     /* states per work-queue task, multiple of 64 (0 = 256) */
+    uint32_t batch_chunk;     /* smallest work-queue task in states, multiple of 64 (0 = 256); a large level is cut
+                                 into about two tasks per wave of the grid, up to 1024 states each */
     int batch_schedule;       /* tw_solve_batch: TW_BATCH_ROUNDS (default) runs level rounds — per round one
                                  launch expands the current level of every running graph (tasks sized
                                  for about two per wave) and a second advances each graph; or

@@ -16,6 +16,7 @@ enum : uint32_t {
 };
 
 constexpr int kBatchKeyBits = 48;   // keys below bit 48, table tag above
+constexpr int kBatchWavesPerBlock = 4;
 constexpr int kBatchMaxN = 48;
 
 // One level of one graph's batched search, recorded in trace mode (a test
@@ -33,7 +34,8 @@ struct BatchTraceRec {
 
 // Per-graph state, device resident.  Written by the host before the launch;
 // afterwards only by the wave that finishes a level of this graph (counters
-// by atomics).
+// by atomics; in the persistent launch every field that changes is stored and
+// loaded with device-scope atomics).
 struct BatchGraph {
     uint64_t adj[64];
     uint64_t *keys;          // arena: the levels of the current bound, back to back
@@ -80,27 +82,36 @@ struct BatchJob {
     uint64_t begin;          // arena offset of the level's first state
     uint64_t count;
     uint32_t nchunks;
+    uint32_t chunk;          // states per chunk
     uint32_t cursor;         // next chunk to hand out (atomic)
     uint32_t done;           // chunks finished (atomic)
-    uint32_t ready;          // 1 once the fields above are written (release/acquire)
+    uint32_t ready;          // 1 once the fields above are written (stored after they completed)
+    uint32_t pad_;
 };
 
+// The words every wave polls (head, tail) and the exit words (active,
+// abort) sit on separate 128-byte lines.
 struct BatchQueue {
     unsigned long long head;      // persistent queue: first job not yet exhausted; level rounds: the round's task size
     unsigned long long tail;      // jobs reserved
     unsigned long long capacity;
+    unsigned long long pad0_[13];
     uint32_t active;              // graphs still running
     uint32_t abort;               // set if a wait exceeded its bound or the job array filled
+    uint32_t pad1_[30];
 };
+static_assert(sizeof(BatchQueue) == 256, "queue lines");
 
 struct BatchArgs {
     BatchGraph *graphs;
     BatchJob *jobs;
     BatchQueue *q;
-    uint32_t chunk;          // states per task (multiple of 64)
+    uint32_t chunk;          // states per task (multiple of 64); the persistent queue's smallest task
     uint32_t max_probe;
     float max_load;          // a level above this fraction of the table overflows
     uint32_t spin_limit;     // sleeps a wave may spend waiting for work before aborting
+    uint32_t nb;             // graphs in the batch
+    uint32_t nwaves;         // waves of the persistent grid
 };
 
 hipError_t launch_batch(const BatchArgs &a, unsigned grid_blocks, hipStream_t s);

@@ -2100,6 +2100,7 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
         J.graph = (int32_t)b;
         J.count = 1;
         J.nchunks = 1;
+        J.chunk = chunk;
         J.ready = 1;
     }
     twk::BatchQueue hq{};
@@ -2124,8 +2125,10 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
     a.chunk = chunk;
     a.max_probe = 1u << 14;
     a.max_load = 0.85f;
-    a.spin_limit = 20u * 1000u * 1000u;
+    a.spin_limit = 8u * 1000u * 1000u;  // idle polls of up to ~4 us each: about half a minute
+    a.nb = (uint32_t)B;
     const unsigned grid = (unsigned)(c->cu_count * twk::batch_blocks_per_cu());
+    a.nwaves = grid * (unsigned)twk::kBatchWavesPerBlock;
     if (c->opt.timing)
         HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
     if (c->opt.batch_schedule == TW_BATCH_PERSISTENT) {
