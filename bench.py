@@ -252,8 +252,10 @@ def batch_config_leg(graphs, label: str, max_states: int, weights: str, reductio
     """Graphs solved per second, plain ascending bounds against the learned
     start bound, on one batch, each graph's levels capped at max_states
     states (a graph whose level would exceed the cap returns TW_ECAPACITY with
-    the size it reached).  Batch options from the autotuner (tuned on the
-    batch's graphs of n <= 32).  Answers must agree on every graph both
+    the size it reached).  Task size, load factor and probe scheme from the
+    autotuner (tuned on the batch's graphs of n <= 32); the schedule is the
+    library's default (the persistent queue, level rounds with the
+    reductions).  Answers must agree on every graph both
     policies solve.  With ceiling: the certifying work alone (decide(tw) and,
     when tw is above the lower bound, decide(tw - 1)) per solved graph, i.e.
     a start bound that is never wrong.  The graphs go in calls of per_call
@@ -269,6 +271,7 @@ def batch_config_leg(graphs, label: str, max_states: int, weights: str, reductio
         base["reductions"] = T.TW_REDUCE_CLIQUE_PATHS
     out = {"label": label, "graphs": len(graphs), "n": [min(len(g) for g in graphs), max(len(g) for g in graphs)],
            "max_states_per_level": max_states, "reductions": reductions, "tuned_options": tuned,
+           "schedule": "level rounds" if reductions else "persistent queue",
            "weights": os.path.relpath(weights, ROOT)}
     res = {}
     out["graphs_per_call"] = per_call

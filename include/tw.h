@@ -104,11 +104,13 @@ typedef struct {
                                     re-solved alone by the tw_solve path */
     uint32_t batch_chunk;     /* smallest work-queue task in states, multiple of 64 (0 = 256); a large level is cut
                                  into about two tasks per wave of the grid, up to 1024 states each */
-    int batch_schedule;       /* tw_solve_batch: TW_BATCH_ROUNDS (default) runs level rounds — per round one
+    int batch_schedule;       /* tw_solve_batch: TW_BATCH_AUTO (default) takes the persistent queue, or level
+                                 rounds when options.reductions is on (its levels are small, and small
+                                 levels favour the rounds); TW_BATCH_PERSISTENT: one persistent launch
+                                 with a device work queue of (graph, level) jobs cut into tasks of at
+                                 least batch_chunk states; TW_BATCH_ROUNDS: level rounds — per round one
                                  launch expands the current level of every running graph (tasks sized
-                                 for about two per wave) and a second advances each graph; or
-                                 TW_BATCH_PERSISTENT, one persistent launch with a device work queue of
-                                 (graph, level) jobs cut into batch_chunk-state tasks */
+                                 for about two per wave) and a second advances each graph */
     int reductions;           /* TW_REDUCE_NONE (default): the levels are those of Listing 1.
                                  TW_REDUCE_CLIQUE_PATHS: the first two optimisations of §3.1 — the
                                  vertices of a maximum clique C are never added to a state (some optimal
@@ -155,7 +157,7 @@ typedef struct {
 enum { TW_CAPTURE_AUTO = 0, TW_CAPTURE_OFF = 1 };
 
 enum { TW_REDUCE_NONE = 0, TW_REDUCE_CLIQUE_PATHS = 1 };
-enum { TW_BATCH_ROUNDS = 0, TW_BATCH_PERSISTENT = 1 };
+enum { TW_BATCH_AUTO = 0, TW_BATCH_ROUNDS = 1, TW_BATCH_PERSISTENT = 2 };
 enum { TW_MMW_NONE = 0, TW_MMW_PRUNE = 1 };
 
 /* Counters of one call (summed over every bound k and level it ran). */
@@ -211,10 +213,10 @@ tw_status tw_solve_noalloc(tw_ctx *ctx, const tw_graph *g, int32_t *out_tw, int3
 /* tw_solve for count graphs of uneven size.  out_tw[count], out_status[count];
  * out_orders holds the orders back to back (sum of n entries, graph order).
  * Graphs with n <= 48 are solved together on the device, each with its own
- * arena (every level of its current bound) and tagged hash table, by level
- * rounds (default: one launch expands the current level of every running
- * graph, a second advances each graph's level or bound) or by one persistent
- * kernel with a device work queue (options.batch_schedule).  Graphs whose
+ * arena (every level of its current bound) and tagged hash table, by one
+ * persistent kernel with a device work queue or by level rounds (one launch
+ * expands the current level of every running graph, a second advances each
+ * graph's level or bound); options.batch_schedule chooses.  Graphs whose
  * levels outgrow their arena get one more batched attempt with four times the
  * arena (level rounds), and then, like the others, the tw_solve path.  The
  * treewidths equal tw_solve's; each order is checked by fill-in to have

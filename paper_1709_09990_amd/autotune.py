@@ -1,6 +1,8 @@
-"""Autotuner for the batched search: schedule (level rounds, or the persistent
-work queue with its states per task), hash-table load factor and probe
-scheme, picked by timing candidates on a sample.
+"""Autotuner for the batched search: the persistent work queue's smallest task,
+hash-table load factor and probe scheme, picked by timing candidates on a
+sample.  The schedule itself is the library's choice (options.batch_schedule
+left at TW_BATCH_AUTO): a sample of small graphs cannot show how large levels
+favour the persistent queue.
 
     from paper_1709_09990_amd import autotune
     opts = autotune.tuned_options(graphs)          # cached per (n bucket, device)
@@ -21,8 +23,8 @@ import numpy as np
 
 from . import tw as T
 
-# 0: level rounds (task size chosen per round); else the persistent queue with that many states per task
-CHUNKS = (0, 128, 256, 512)
+# smallest persistent-queue task, in states (larger levels are cut into larger tasks)
+CHUNKS = (64, 128, 256)
 LOAD_FACTORS = (0.4, 0.5, 0.7)
 PROBES = (1, 2)
 
@@ -64,8 +66,7 @@ def tune(graphs, reps: int = 2, log=None) -> dict:
     results = []
     ref = None
     for chunk, lf, probe in itertools.product(CHUNKS, LOAD_FACTORS, PROBES):
-        opts = {"batch_schedule": T.TW_BATCH_ROUNDS if chunk == 0 else T.TW_BATCH_PERSISTENT,
-                "batch_chunk": chunk, "load_factor": lf, "probe": probe}
+        opts = {"batch_chunk": chunk, "load_factor": lf, "probe": probe}
         dt, tws = _time(graphs, opts, reps)
         if ref is None:
             ref = tws

@@ -38,6 +38,8 @@ struct BatchTraceRec {
 // loaded with device-scope atomics).
 struct BatchGraph {
     uint64_t adj[64];
+    uint64_t adjk[64];       // adjacency the current bound expands with: adj, plus with paths the
+                             // pairs joined by more than k disjoint paths (set per bound)
     uint64_t *keys;          // arena: the levels of the current bound, back to back
     uint8_t *lastv;
     uint32_t *parent;        // per state: index of the state it came from, within the level below
@@ -75,12 +77,17 @@ struct BatchGraph {
     int32_t pad_;
 };
 
-// One level of one graph: nchunks tasks of up to chunk states.
+// One level of one graph: nchunks tasks of up to chunk states.  It carries
+// the graph fields every task needs (bound, table tag, where the next level
+// starts), so a task reads them with the job.
 struct BatchJob {
     int32_t graph;
     int32_t level;
     uint64_t begin;          // arena offset of the level's first state
     uint64_t count;
+    uint64_t out_base;       // arena offset of the next level
+    int32_t k;
+    uint32_t tag;
     uint32_t nchunks;
     uint32_t chunk;          // states per chunk
     uint32_t cursor;         // next chunk to hand out (atomic)

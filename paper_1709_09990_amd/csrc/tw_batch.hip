@@ -99,7 +99,8 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t z)
 
 // Called by one lane: append a job for (g, level).
 template <bool C>
-__device__ void push_job(const BatchArgs &a, int g, int level, uint64_t begin, uint64_t count)
+__device__ void push_job(const BatchArgs &a, int g, int level, uint64_t begin, uint64_t count, int k, uint32_t tag,
+                         uint64_t out_base)
 {
     if (!a.jobs)
         return;  // level rounds: the graph's level fields are the next round's work
@@ -113,6 +114,9 @@ __device__ void push_job(const BatchArgs &a, int g, int level, uint64_t begin, u
     stc<C>(&j->level, (int32_t)level);
     stc<C>(&j->begin, begin);
     stc<C>(&j->count, count);
+    stc<C>(&j->out_base, out_base);
+    stc<C>(&j->k, (int32_t)k);
+    stc<C>(&j->tag, tag);
     // about 64 tasks for a large level (up to kMaxTask states each), so that
     // the graphs running together give every wave work in large pieces;
     // never below the task size the caller chose
@@ -172,20 +176,40 @@ __device__ void graph_done(const BatchArgs &a, BatchGraph *G, uint32_t status, i
 }
 
 // Restart graph G at level 0 of bound k (lane 0 writes, then publishes the job).
+// Whole wave: lane j's row of the adjacency bound k expands with.
+template <bool C>
+__device__ void set_bound_rows(BatchGraph *G, int k, int lane)
+{
+    const int n = G->n;
+    const uint8_t *paths = G->paths;
+    if (!paths || lane >= n)
+        return;
+    // edges of G_k+: pairs joined by more than k disjoint paths (§3.1)
+    uint64_t row = G->adj[lane];
+    const uint8_t *cnt = paths + lane * 64;
+    for (int u = 0; u < n; ++u)
+        if ((int)cnt[u] > k)
+            row |= 1ull << u;
+    stc<C>(&G->adjk[lane], row);
+}
+
 template <bool C>
 __device__ void start_bound(const BatchArgs &a, BatchGraph *G, int g, int k, int lane)
 {
+    set_bound_rows<C>(G, k, lane);
     if (lane == 0) {
+        const uint32_t tag = ldc<C>(&G->tag) + 1u;
         stc<C>(&G->k, (int32_t)k);
         stc<C>(&G->decisions, ldc<C>(&G->decisions) + 1u);
         stc<C>(&G->L, (int32_t)(G->n - k - 1));
         stc<C>(&G->level, 0);
-        stc<C>(&G->tag, ldc<C>(&G->tag) + 1u);
+        stc<C>(&G->tag, tag);
         stc<C>(&G->out_count, 0ull);
         stc<C>(&G->peak_k, 1ull);
         stc<C>(&G->level_off[0], (uint64_t)0);
         stc<C>(&G->level_off[1], (uint64_t)1);  // level 0 is the empty set (never read from the arena)
-        push_job<C>(a, g, 0, 0, 1);
+        // the job is published after every lane's row (the drain waits for the whole wave)
+        push_job<C>(a, g, 0, 0, 1, k, tag, 1);
     }
 }
 
@@ -264,7 +288,7 @@ __device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_c
             stc<C>(&G->level, (int32_t)next);
             stc<C>(&G->tag, tag + 1u);
             stc<C>(&G->out_count, 0ull);
-            push_job<C>(a, g, next, next_off, cnt);
+            push_job<C>(a, g, next, next_off, cnt, k, tag + 1u, next_off + cnt);
         }
         return;
     }
@@ -290,14 +314,13 @@ __device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_c
 // graph's tagged table, append the new ones to its next level.  Whole wave.
 template <bool C>
 __device__ void process_chunk(const BatchArgs &a, int g, int level, uint64_t begin, uint64_t lo, uint64_t hi,
-                              int lane, uint64_t *stage_key, uint8_t *stage_v, uint32_t *stage_p)
+                              int k, uint32_t tag32, uint64_t out_base, int lane, uint64_t *stage_key,
+                              uint8_t *stage_v, uint32_t *stage_p)
 {
     BatchGraph *G = &a.graphs[g];
     const int n = (int)first_lane32((uint32_t)G->n);
-    const int k = (int)first_lane32((uint32_t)ldc<C>(&G->k));
-    const uint64_t tag = (uint64_t)first_lane32(ldc<C>(&G->tag)) << kBatchKeyBits;
+    const uint64_t tag = (uint64_t)tag32 << kBatchKeyBits;
     const uint64_t tslots = read_lane64(G->table_slots, 0);
-    const uint64_t out_base = read_lane64(ldc<C>(&G->level_off[level + 1]), 0);
     const uint64_t arena_cap = read_lane64(G->arena_cap, 0);
     const uint64_t max_fill = (uint64_t)((double)tslots * a.max_load);
     // reads stay inside the arena whatever the level fields hold
@@ -309,15 +332,7 @@ __device__ void process_chunk(const BatchArgs &a, int g, int level, uint64_t beg
     uint8_t *lastv = G->lastv;
     uint32_t *parent = G->parent;
     uint64_t *table = G->table;
-    uint64_t Aj = lane < n ? G->adj[lane] : 0ull;
-    const uint8_t *paths = G->paths;
-    if (paths && lane < n) {
-        // edges of G_k+: pairs joined by more than k disjoint paths (§3.1)
-        const uint8_t *row = paths + lane * 64;
-        for (int u = 0; u < n; ++u)
-            if ((int)row[u] > k)
-                Aj |= 1ull << u;
-    }
+    const uint64_t Aj = lane < n ? ldc<C>(&G->adjk[lane]) : 0ull;
     const bool lane_allowed = ((G->allowed >> lane) & 1ull) != 0ull;
     const uint64_t lanebit = 1ull << lane;
     const bool tracing = G->trace != nullptr;
@@ -502,6 +517,9 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
         const int level = (int)first_lane32((uint32_t)ldc<true>(&J->level));
         const uint64_t begin = read_lane64(ldc<true>(&J->begin), 0);
         const uint64_t count = read_lane64(ldc<true>(&J->count), 0);
+        const uint64_t out_base = read_lane64(ldc<true>(&J->out_base), 0);
+        const int k = (int)first_lane32((uint32_t)ldc<true>(&J->k));
+        const uint32_t tag = first_lane32(ldc<true>(&J->tag));
         if ((uint32_t)g >= a.nb || level < 0 || level > 63) {
             if (lane == 0)
                 atomicOr(&a.q->abort, 1u);  // a job that names no graph: stop, the host reports it
@@ -510,7 +528,8 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
         const uint64_t per = (uint64_t)first_lane32(ldc<true>(&J->chunk));
         const uint64_t lo = (uint64_t)c * per;
         const uint64_t hi = lo + per < count ? lo + per : count;
-        process_chunk<true>(a, g, level, begin, lo, hi, lane, stage_key[wv], stage_v[wv], stage_p[wv]);
+        process_chunk<true>(a, g, level, begin, lo, hi, k, tag, out_base, lane, stage_key[wv], stage_v[wv],
+                            stage_p[wv]);
         drain();  // this chunk's states and counters are complete before it counts as done
         uint32_t d = 0;
         if (lane == 0)
@@ -610,7 +629,11 @@ __global__ __launch_bounds__(kBatchBlock) void round_kernel(BatchArgs a, uint32_
         const uint64_t count = read_lane64(G->level_off[level + 1], 0) - begin;
         const uint64_t first = (uint64_t)(t - task_start[lo]) * c;
         const uint64_t last = first + c < count ? first + c : count;
-        process_chunk<false>(a, (int)lo, level, begin, first, last, lane, stage_key[wv], stage_v[wv], stage_p[wv]);
+        const int k = (int)first_lane32((uint32_t)G->k);
+        const uint32_t tag = first_lane32(G->tag);
+        const uint64_t out_base = read_lane64(G->level_off[level + 1], 0);
+        process_chunk<false>(a, (int)lo, level, begin, first, last, k, tag, out_base, lane, stage_key[wv],
+                             stage_v[wv], stage_p[wv]);
     }
 }
 

@@ -1321,12 +1321,19 @@ tw_status captured_decide(tw_ctx *c, Captured &cp, const Graph &g, int k, uint64
                               c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     rs.launches++;
+    // a table overflow, or a level above max_states (whose slot held it all):
+    // the bound runs on the host-driven loop, which reports the cap
+    for (int j = 0; j < L; ++j) {
+        const LevelCounters &lc = h->ctr[j];
+        if (lc.overflow || (c->opt.max_states && lc.out_count > c->opt.max_states))
+            return kNotCaptured;
+        if (lc.out_count == 0)
+            break;
+    }
     uint64_t cur = 1, run_peak = 1;
     int i = 0;
     for (; i < L; ++i) {
         const LevelCounters &lc = h->ctr[i];
-        if (lc.overflow)
-            return kNotCaptured;
         const uint64_t in_count = cur, out_count = lc.out_count;
         rs.states_expanded += in_count;
         rs.expansions += in_count * (uint64_t)(n - i);
@@ -1990,6 +1997,15 @@ struct BatchTrace {
 // tw, order and outcome; graphs whose arena or table filled up are appended
 // to single_ids for the tw_solve path.
 
+// The batch schedule a call runs: TW_BATCH_AUTO takes the persistent queue,
+// or level rounds with the reductions (their small levels favour the rounds).
+int batch_schedule_of(const tw_ctx *c)
+{
+    if (c->opt.batch_schedule != TW_BATCH_AUTO)
+        return c->opt.batch_schedule;
+    return c->opt.reductions == TW_REDUCE_CLIQUE_PATHS ? TW_BATCH_ROUNDS : TW_BATCH_PERSISTENT;
+}
+
 tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<Reduction> *reds,
                        const std::vector<int> &lbs,
                        const std::vector<int> &k0s, const std::vector<uint64_t> &arenas,
@@ -2089,16 +2105,26 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
             G.trace = (twk::BatchTraceRec *)d_trace.p + b * tcap;
             G.trace_cap = (uint32_t)tcap;
         }
+        for (int j = 0; j < g.n; ++j)
+            G.adjk[j] = g.rows[j];
         if (reds) {
             const Reduction &r = (*reds)[(size_t)t];
             G.allowed = ~r.clique;
             std::memcpy(hpaths.data() + b * 64 * 64, r.paths.data(), 64 * 64);
             G.paths = (const uint8_t *)d_paths.p + b * 64 * 64;
+            // the first bound's rows; later bounds set theirs on the device
+            for (int j = 0; j < g.n; ++j)
+                for (int u = 0; u < g.n; ++u)
+                    if ((int)r.paths[(size_t)j * 64 + u] > G.k)
+                        G.adjk[j] |= 1ull << u;
         }
         twk::BatchJob &J = hj[b];
         std::memset(&J, 0, sizeof J);
         J.graph = (int32_t)b;
         J.count = 1;
+        J.out_base = 1;
+        J.k = G.k;
+        J.tag = G.tag;
         J.nchunks = 1;
         J.chunk = chunk;
         J.ready = 1;
@@ -2131,7 +2157,7 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
     a.nwaves = grid * (unsigned)twk::kBatchWavesPerBlock;
     if (c->opt.timing)
         HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-    if (c->opt.batch_schedule == TW_BATCH_PERSISTENT) {
+    if (batch_schedule_of(c) == TW_BATCH_PERSISTENT) {
         HIP_TRY(c, twk::launch_batch(a, grid, c->stream));
     } else {
         // level rounds until no graph runs; the host looks every 8 rounds
@@ -2391,7 +2417,8 @@ tw_status tw_ctx_create(const tw_options *options, tw_ctx **out)
     if ((c->opt.dedup != TW_DEDUP_EXACT && c->opt.dedup != TW_DEDUP_BLOOM &&
          c->opt.dedup != TW_DEDUP_BLOOM_CERTIFIED) ||
         (c->opt.reductions != TW_REDUCE_NONE && c->opt.reductions != TW_REDUCE_CLIQUE_PATHS) ||
-        (c->opt.batch_schedule != TW_BATCH_ROUNDS && c->opt.batch_schedule != TW_BATCH_PERSISTENT) ||
+        (c->opt.batch_schedule != TW_BATCH_AUTO && c->opt.batch_schedule != TW_BATCH_ROUNDS &&
+         c->opt.batch_schedule != TW_BATCH_PERSISTENT) ||
         (c->opt.mmw_prune != TW_MMW_NONE && c->opt.mmw_prune != TW_MMW_PRUNE)) {
         delete c;
         return TW_EINVAL;
@@ -2948,8 +2975,8 @@ tw_status solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t *ou
         return st;
     // graphs whose levels outgrew their arena: once more together, with 4x the
     // arena (up to kArenaRetry states), before the one-at-a-time path (level
-    // rounds only: the persistent queue measured slower with the retry)
-    if (library_arena && c->opt.batch_schedule == TW_BATCH_ROUNDS && single_ids.size() > before) {
+    // rounds only)
+    if (library_arena && batch_schedule_of(c) == TW_BATCH_ROUNDS && single_ids.size() > before) {
         std::vector<int> retry(single_ids.begin() + (long)before, single_ids.end());
         single_ids.resize(before);
         std::vector<int> again;

@@ -19,7 +19,7 @@ TW_OK, TW_EINVAL, TW_ENOMEM, TW_EDEVICE, TW_ECAPACITY = range(5)
 TW_DEDUP_EXACT, TW_DEDUP_BLOOM, TW_DEDUP_BLOOM_CERTIFIED = 0, 1, 2
 TW_K_ASCENDING, TW_K_LEARNED = 0, 1
 TW_REDUCE_NONE, TW_REDUCE_CLIQUE_PATHS = 0, 1
-TW_BATCH_ROUNDS, TW_BATCH_PERSISTENT = 0, 1
+TW_BATCH_AUTO, TW_BATCH_ROUNDS, TW_BATCH_PERSISTENT = 0, 1, 2
 TW_MMW_NONE, TW_MMW_PRUNE = 0, 1
 TW_CAPTURE_AUTO, TW_CAPTURE_OFF = 0, 1
 
@@ -304,7 +304,7 @@ class Context:
                  load_factor: float = 0.0, max_states: int = 0, capacity_override: int = 0,
                  timing: bool = False, k_policy: int = TW_K_ASCENDING, weights_path: str | None = None,
                  batch_graph_states: int = 0, batch_chunk: int = 0, probe: int = 0, partition: int = 0,
-                 reductions: int = TW_REDUCE_NONE, batch_schedule: int = TW_BATCH_ROUNDS,
+                 reductions: int = TW_REDUCE_NONE, batch_schedule: int = TW_BATCH_AUTO,
                  mmw_prune: int = TW_MMW_NONE, workspace: int = 0, workspace_bytes: int = 0,
                  fault_inject_level: int = 0, capture: int = 0):
         L = load()

@@ -98,7 +98,7 @@ def test_batch_levels_after_arena_retry(oracle):
     from paper_1709_09990_amd import tw as T
     graphs = G.workload_batch(64, seed0=42000, n_lo=12, n_hi=22)
     cache = _CACHE
-    with T.Context(device=0) as c:
+    with T.Context(device=0, batch_schedule=T.TW_BATCH_ROUNDS) as c:
         tws, per, batched, _ = _run(c, oracle, graphs, cache, first_arena=2048)
     # graphs batched although one bound's levels hold more than the first arena
     retried = 0

@@ -358,13 +358,13 @@ def test_batch_graph_stats_peak(oracle):
 
 
 def test_autotune_candidates_agree(tmp_path, monkeypatch):
-    """Every autotuner candidate (schedule and tile size, load factor, probe
-    scheme) gives the same answers; the tuned choice is cached and reused."""
+    """Every autotuner candidate (task size, load factor, probe scheme) gives
+    the same answers; the tuned choice is cached and reused."""
     from paper_1709_09990_amd import autotune
     monkeypatch.setenv("TW_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     graphs = G.workload_batch(24, seed0=36000, n_lo=10, n_hi=22)
     opts = autotune.tuned_options(graphs, sample=24)
-    assert set(opts) == {"batch_schedule", "batch_chunk", "load_factor", "probe"}
+    assert set(opts) == {"batch_chunk", "load_factor", "probe"}
     assert autotune.tuned_options(graphs) == opts
 
 
@@ -424,7 +424,7 @@ def test_bloom_certified_answers_are_exact(oracle):
 
 def test_invalid_options_rejected():
     from paper_1709_09990_amd import tw as T
-    for kw in ({"dedup": 5}, {"reductions": 3}, {"batch_schedule": 2}):
+    for kw in ({"dedup": 5}, {"reductions": 3}, {"batch_schedule": 3}):
         with pytest.raises(T.TwError) as e:
             T.Context(device=0, **kw)
         assert e.value.status == T.TW_EINVAL
