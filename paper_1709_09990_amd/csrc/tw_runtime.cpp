@@ -2974,9 +2974,8 @@ tw_status solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t *ou
     if (st != TW_OK)
         return st;
     // graphs whose levels outgrew their arena: once more together, with 4x the
-    // arena (up to kArenaRetry states), before the one-at-a-time path (level
-    // rounds only)
-    if (library_arena && batch_schedule_of(c) == TW_BATCH_ROUNDS && single_ids.size() > before) {
+    // arena (up to kArenaRetry states), before the one-at-a-time path
+    if (library_arena && single_ids.size() > before) {
         std::vector<int> retry(single_ids.begin() + (long)before, single_ids.end());
         single_ids.resize(before);
         std::vector<int> again;
