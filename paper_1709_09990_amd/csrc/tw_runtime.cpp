@@ -11,10 +11,13 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cmath>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -2335,6 +2338,7 @@ constexpr uint64_t kArenaMax = 1ull << 23;
 constexpr int kLearnedMaxN = 40;
 // arena of the second batched attempt for graphs that outgrew the first
 constexpr uint64_t kArenaRetry = 1ull << 24;
+constexpr int kSingleWorkers = 4;  // worker contexts of the single-graph path in tw_solve_batch
 
 tw_status predict_starts(tw_ctx *c, const std::vector<Graph> &graphs, const std::vector<int> &lbs,
                          const std::vector<int> &ids, std::vector<int> &k0s, std::vector<uint64_t> &arena_of,
@@ -2907,66 +2911,120 @@ tw_status solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t *ou
     }
     const std::vector<Reduction> *rp = c->opt.reductions ? &reds : nullptr;
 
-    // Graphs already bound for the single-graph path (above the batched size,
-    // Bloom dedup, or predicted too large for an arena) run on a second
-    // context and stream, concurrently with the batched search.
-    struct Aux {
-        tw_ctx *ctx = nullptr;
-        std::thread th;
-        RunStats rs;
+    // Graphs for the single-graph path run on a pool of worker contexts, each
+    // with its own stream and host thread (one per hardware queue): those known
+    // before the batch starts (above the batched size, Bloom dedup, or predicted
+    // too large for an arena) beside the batched search, those that outgrow
+    // their arena after it, largest first.  One graph's small levels leave most
+    // of the GPU idle; several graphs at once fill it.  A graph that runs out of
+    // memory beside the others is solved again alone at the end.  With a
+    // caller's workspace they run one at a time on this context.
+    struct Pool {
+        std::vector<tw_ctx *> ctxs;
+        std::vector<RunStats> rs;
+        std::vector<std::thread> th;
+        std::mutex m;
+        std::condition_variable cv;
+        std::deque<int> q;
+        bool closed = false;
         tw_status status = TW_OK;
         std::string err;
-        ~Aux()
+        void finish()
         {
-            if (th.joinable())
-                th.join();
-            if (ctx)
-                tw_ctx_destroy(ctx);
+            {
+                std::lock_guard<std::mutex> g(m);
+                closed = true;
+            }
+            cv.notify_all();
+            for (std::thread &t : th)
+                if (t.joinable())
+                    t.join();
         }
-    } aux;
-    if (!single_ids.empty() && !batch_ids.empty() && !c->carve) {
+        ~Pool()
+        {
+            {
+                std::lock_guard<std::mutex> g(m);
+                q.clear();  // an early return: the queued graphs are not needed
+            }
+            finish();
+            for (tw_ctx *x : ctxs)
+                tw_ctx_destroy(x);
+        }
+    } pool;
+    auto worker = [&](size_t w) {
+        if (hipSetDevice(c->device) != hipSuccess) {
+            std::lock_guard<std::mutex> g(pool.m);
+            if (pool.status == TW_OK) {
+                pool.status = TW_EDEVICE;
+                pool.err = "hipSetDevice failed on a worker context";
+            }
+            return;
+        }
+        for (;;) {
+            int t;
+            {
+                std::unique_lock<std::mutex> lk(pool.m);
+                pool.cv.wait(lk, [&]() { return pool.closed || !pool.q.empty(); });
+                if (pool.q.empty())
+                    return;
+                t = pool.q.front();
+                pool.q.pop_front();
+            }
+            GraphOutcome oc;
+            tw_status s = solve_one(pool.ctxs[w], graphs[(size_t)t], rp ? &reds[(size_t)t] : nullptr,
+                                    lbs[(size_t)t], k0s[(size_t)t], &out_tw[t], out_orders + offs[(size_t)t],
+                                    pool.rs[w], &oc);
+            out_status[t] = s;
+            outcomes[(size_t)t] = oc;
+            if (s != TW_OK)
+                out_tw[t] = -1;
+            if (s == TW_EDEVICE) {
+                std::lock_guard<std::mutex> g(pool.m);
+                if (pool.status == TW_OK) {
+                    pool.status = s;
+                    pool.err = pool.ctxs[w]->err;
+                }
+                pool.q.clear();
+                pool.closed = true;
+                pool.cv.notify_all();
+                return;
+            }
+        }
+    };
+    // the workers, on first need (none with a caller's workspace, or if no
+    // context can be made: the graphs then run below on this context)
+    auto start_pool = [&]() {
+        if (!pool.ctxs.empty() || c->carve)
+            return;
         tw_options o = c->opt;
         o.stream = nullptr;
         o.k_policy = TW_K_ASCENDING;  // starts are already chosen
         o.weights_path = nullptr;
-        if (tw_ctx_create(&o, &aux.ctx) == TW_OK) {
-            std::vector<int> early;
-            early.swap(single_ids);
-            aux.th = std::thread([&, early]() {
-                if (hipSetDevice(c->device) != hipSuccess) {
-                    aux.status = TW_EDEVICE;
-                    aux.err = "hipSetDevice failed on the second context";
-                    return;
-                }
-                for (int t : early) {
-                    GraphOutcome oc;
-                    tw_status s = solve_one(aux.ctx, graphs[(size_t)t], rp ? &reds[(size_t)t] : nullptr,
-                                            lbs[(size_t)t], k0s[(size_t)t], &out_tw[t],
-                                            out_orders + offs[(size_t)t], aux.rs, &oc);
-                    out_status[t] = s;
-                    outcomes[(size_t)t] = oc;
-                    if (s != TW_OK)
-                        out_tw[t] = -1;
-                    if (s == TW_EDEVICE) {
-                        aux.status = s;
-                        aux.err = aux.ctx->err;
-                        return;
-                    }
-                }
-            });
-        } else {
-            aux.ctx = nullptr;  // no second context: they run below on this one
+        for (int w = 0; w < kSingleWorkers; ++w) {
+            tw_ctx *x = nullptr;
+            if (tw_ctx_create(&o, &x) != TW_OK)
+                break;
+            pool.ctxs.push_back(x);
         }
-    }
-    auto join_aux = [&]() -> tw_status {
-        if (aux.th.joinable())
-            aux.th.join();
-        add_run_stats(rs, aux.rs);
-        aux.rs = RunStats{};
-        if (aux.status != TW_OK)
-            return fail(c, aux.status, "%s", aux.err.c_str());
-        return TW_OK;
+        pool.rs.resize(pool.ctxs.size());
+        for (size_t w = 0; w < pool.ctxs.size(); ++w)
+            pool.th.emplace_back(worker, w);
     };
+    auto enqueue = [&](std::vector<int> &ids) {
+        if (ids.empty())
+            return;
+        start_pool();
+        if (pool.ctxs.empty())
+            return;  // they stay in ids, for this context
+        std::stable_sort(ids.begin(), ids.end(), [&](int x, int y) { return graphs[(size_t)x].n > graphs[(size_t)y].n; });
+        {
+            std::lock_guard<std::mutex> g(pool.m);
+            pool.q.insert(pool.q.end(), ids.begin(), ids.end());
+        }
+        pool.cv.notify_all();
+        ids.clear();
+    };
+    enqueue(single_ids);
 
     const size_t before = single_ids.size();
     st = batch_run(c, graphs, rp, lbs, k0s, arena_of, batch_ids, out_tw, out_orders, offs, out_status,
@@ -2992,6 +3050,7 @@ tw_status solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t *ou
         if (st != TW_OK)
             return st;
     }
+    enqueue(single_ids);
     for (int t : single_ids) {
         GraphOutcome oc;
         tw_status s = solve_one(c, graphs[(size_t)t], rp ? &reds[(size_t)t] : nullptr, lbs[(size_t)t],
@@ -3004,11 +3063,13 @@ tw_status solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t *ou
         if (s == TW_EDEVICE)
             return s;
     }
-    st = join_aux();
-    if (st != TW_OK)
-        return st;
-    // graphs the second context could not fit beside the batched search: once
-    // more here, now that the batch's memory is free
+    pool.finish();
+    for (const RunStats &w : pool.rs)
+        add_run_stats(rs, w);
+    if (pool.status != TW_OK)
+        return fail(c, pool.status, "%s", pool.err.c_str());
+    // graphs a worker could not fit beside the batched search or the other
+    // workers: once more here, alone
     for (uint32_t t = 0; t < count; ++t) {
         if (out_status[t] != TW_ENOMEM || graphs[t].n == 0)
             continue;
