@@ -19,16 +19,21 @@
 //
 // Hand-over between waves of the persistent launch.  On this part each XCD
 // has its own L2, so an agent-scope acquire invalidates the fetching XCD's
-// L2 and a release writes it back (buffer_inv / buffer_wbl2): paid per task,
-// and per poll while waves wait for work, that maintenance dominated the
-// launch.  Instead every value one wave hands to another (arena states, job
-// and per-graph fields) is stored and loaded with device-scope relaxed
-// atomics, which the compiler emits as single sc1 accesses that are coherent
-// across the XCDs with no cache maintenance; a writer drains its memory
-// counters (every earlier access complete at device scope) before the atomic
-// that publishes the data, and a reader loads the data only after the atomic
-// that shows it published.  Counters stay read-modify-write atomics.  Level
-// rounds use plain accesses: the kernel boundaries order their levels.
+// L2 and a release writes it back (buffer_inv / buffer_wbl2), which would be
+// paid per task and per poll.  That maintenance exists to make plain
+// accesses coherent.  Here every value one wave hands to another (arena
+// states, job and per-graph fields) is instead stored and loaded with
+// device-scope relaxed atomics, which the compiler emits as single sc1
+// accesses, each coherent across the XCDs by itself.  What remains is order:
+// a writer drains its memory counters (s_waitcnt 0: every earlier access,
+// stores included, complete at device scope; the same wait a release makes)
+// before the atomic that publishes the data, and a reader issues its loads
+// only after the atomic that shows the data published.  Compiler barriers
+// keep the compiler from moving accesses across either point.  Counters stay
+// read-modify-write atomics.  Idle waves poll two words and rescan the job
+// window only when it changed, so that waiting takes little from the memory
+// system the working waves probe.  Level rounds use plain accesses: the
+// kernel boundaries order their levels.
 #include "tw_batch.h"
 #include "tw_wave.h"
 
