@@ -77,7 +77,7 @@ struct BatchGraph {
     int32_t pad_;
 };
 
-// One level of one graph: nchunks tasks of up to chunk states.  It carries
+// One level of one graph: ready tasks of up to chunk states.  It carries
 // the graph fields every task needs (bound, table tag, where the next level
 // starts), so a task reads them with the job.
 struct BatchJob {
@@ -88,12 +88,12 @@ struct BatchJob {
     uint64_t out_base;       // arena offset of the next level
     int32_t k;
     uint32_t tag;
-    uint32_t nchunks;
     uint32_t chunk;          // states per chunk
     uint32_t cursor;         // next chunk to hand out (atomic)
     uint32_t done;           // chunks finished (atomic)
-    uint32_t ready;          // 1 once the fields above are written (stored after they completed)
-    uint32_t pad_;
+    uint32_t ready;          // 0, then the number of chunks once the fields above are written
+                             // (stored after they completed): one load tells both
+    uint32_t pad_[2];
 };
 
 // The words every wave polls (head, tail) and the exit words (active,

@@ -129,11 +129,11 @@ __device__ void push_job(const BatchArgs &a, int g, int level, uint64_t begin, u
     per = (per + 63) / 64 * 64;
     per = per < a.chunk ? a.chunk : (per > kMaxTask ? (a.chunk > kMaxTask ? a.chunk : kMaxTask) : per);
     stc<C>(&j->chunk, (uint32_t)per);
-    stc<C>(&j->nchunks, (uint32_t)((count + per - 1) / per));
+    const uint32_t nchunks = (uint32_t)((count + per - 1) / per);
     // this job's fields, and the graph fields written before it, are complete
     // before ready shows
     drain();
-    __hip_atomic_store(&j->ready, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&j->ready, nchunks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Whole wave, after a YES at bound G->k with G->L levels in the arena: follow
@@ -240,33 +240,34 @@ __device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_c
     const uint64_t next_off = read_lane64(ldc<C>(&G->level_off[next]), 0);
     const int n = G->n;
     if (lane == 0) {
+        // counters the host reads after the launch (and peak_k, which this
+        // wave reads back at a YES): atomics that return nothing, so no wait
+        atomicAdd(&G->states, (unsigned long long)in_count);
+        atomicAdd(&G->expansions, (unsigned long long)(in_count * (uint64_t)(n - level)));
+        atomicAdd(&G->levels_run, 1u);
+        atomicAdd(&G->unique, (unsigned long long)cnt);
+        atomicMax(&G->peak, (unsigned long long)cnt);
+        atomicMax(&G->peak_k, (unsigned long long)cnt);
         if (G->trace) {
             // record level+1 of bound k, then start the next level's digests
-            // (before any job of this graph is published below)
-            const uint32_t len = ldc<C>(&G->trace_len);
+            // (every chunk of the level is done and no job of its next level
+            // is published yet, so nothing else touches them now)
+            const uint32_t len = atomicAdd(&G->trace_len, 1u);
+            const unsigned long long dsum = atomicExch(&G->digest_sum, 0ull);
+            const unsigned long long dxor = atomicExch(&G->digest_xor, 0ull);
             const unsigned long long succ = ldc<C>(&G->successors);
+            const unsigned long long mark = ldc<C>(&G->succ_mark);
             if (len < G->trace_cap) {
                 BatchTraceRec *r = &G->trace[len];
                 stc<C>(&r->k, (int32_t)k);
                 stc<C>(&r->level, (int32_t)next);
                 stc<C>(&r->count, cnt);
-                stc<C>(&r->successors, (uint64_t)(succ - ldc<C>(&G->succ_mark)));
-                stc<C>(&r->digest_sum, (uint64_t)ldc<C>(&G->digest_sum));
-                stc<C>(&r->digest_xor, (uint64_t)ldc<C>(&G->digest_xor));
+                stc<C>(&r->successors, (uint64_t)(succ - mark));
+                stc<C>(&r->digest_sum, (uint64_t)dsum);
+                stc<C>(&r->digest_xor, (uint64_t)dxor);
             }
-            stc<C>(&G->trace_len, len + 1u);
-            stc<C>(&G->digest_sum, 0ull);
-            stc<C>(&G->digest_xor, 0ull);
             stc<C>(&G->succ_mark, succ);
         }
-        stc<C>(&G->states, ldc<C>(&G->states) + in_count);
-        stc<C>(&G->expansions, ldc<C>(&G->expansions) + in_count * (uint64_t)(n - level));
-        stc<C>(&G->levels_run, ldc<C>(&G->levels_run) + 1u);
-        stc<C>(&G->unique, ldc<C>(&G->unique) + cnt);
-        if (cnt > ldc<C>(&G->peak))
-            stc<C>(&G->peak, (unsigned long long)cnt);
-        if (cnt > ldc<C>(&G->peak_k))
-            stc<C>(&G->peak_k, (unsigned long long)cnt);
     }
     if (ovf || tag >= 0xFFFEu || next == G->fault_level) {
         graph_done<C>(a, G, kBatchFallback, lane);
@@ -470,13 +471,13 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
             for (uint32_t q = 0; q < span; ++q) {
                 const uint64_t jid = h + (gw + q) % span;
                 BatchJob *cand = &a.jobs[jid];
-                if (first_lane32(ld_relaxed(&cand->ready)) == 0) {
+                const uint32_t nc = first_lane32(ld_relaxed(&cand->ready));  // chunks, once published
+                if (nc == 0) {
                     unpublished = true;
                     continue;
                 }
-                // the job's fields are read only after its ready flag was seen
+                // the job's fields are read only after it was seen published
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                const uint32_t nc = first_lane32(ldc<true>(&cand->nchunks));
                 if (first_lane32(ld_relaxed(&cand->cursor)) < nc) {
                     uint32_t got = 0;
                     if (lane == 0)

@@ -2128,9 +2128,8 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
         J.out_base = 1;
         J.k = G.k;
         J.tag = G.tag;
-        J.nchunks = 1;
         J.chunk = chunk;
-        J.ready = 1;
+        J.ready = 1;  // one chunk: the empty set
     }
     twk::BatchQueue hq{};
     hq.tail = B;
