@@ -104,12 +104,14 @@ WEIGHTS = os.path.join(ROOT, "paper_1709_09990_amd", "weights", "mpnn_mixture_n1
 WEIGHTS_REDUCED = os.path.join(ROOT, "paper_1709_09990_amd", "weights", "mpnn_mixture_n16_30_reduced.bin")
 
 
-def probe_reference(kernel_successors_per_s: float) -> dict:
+def probe_reference(kernel_successors_per_s: float, kernel_claims_per_s: float = 0.0) -> dict:
     """The machine's rate for the insert's access pattern, measured now with
     tw_probe_rate on an 8 GiB buffer (far above the 256 MB Infinity Cache, as
     the large levels' tables are): random 16-byte loads with one in flight per
     lane (the probe), random 64-bit compare-and-swaps, and loads with eight in
-    flight per lane.  The expansion kernel does one probe per feasible pair."""
+    flight per lane.  The expansion kernel does one probe per feasible pair,
+    and one winning compare-and-swap per new state (claims: a lower bound on
+    its compare-and-swap rate, since a lost race costs one more)."""
     from paper_1709_09990_amd import tw as T
     nbytes, count = 8 << 30, 1 << 31
     r = {"buffer_bytes": nbytes, "operations": count}
@@ -118,6 +120,9 @@ def probe_reference(kernel_successors_per_s: float) -> dict:
         r[name] = T.probe_rate(nbytes, count, mode)
     r["kernel_probes_per_s"] = kernel_successors_per_s
     r["kernel_frac_of_random_loads"] = round(kernel_successors_per_s / r["random_16B_loads_per_s"], 4)
+    if kernel_claims_per_s:
+        r["kernel_claims_per_s"] = kernel_claims_per_s
+        r["kernel_claims_frac_of_random_cas"] = round(kernel_claims_per_s / r["random_cas64_per_s"], 4)
     return r
 
 
@@ -378,6 +383,8 @@ def large_leg(cap_log2: int = 29) -> dict:
         ks = st.get("kernel_seconds", 0.0)
         out[name] = {"outcome": status, "seconds": round(dt, 2), "levels": st.get("levels"),
                      "peak_level": st.get("peak_frontier"), "expansions": st.get("expansions"),
+                     "states_expanded": st.get("states_expanded"), "successors": st.get("successors"),
+                     "unique": st.get("unique"), "launches": st.get("launches"),
                      "kernel_seconds": round(ks, 3),
                      "kernel_expansions_per_s": st.get("expansions", 0) / ks if ks else None}
         print(json.dumps({"leg": "large_n64", name: out[name]}), flush=True)
@@ -507,9 +514,14 @@ def main():
     ap.add_argument("--reduce-batches", action="store_true", help="run the two legs above with the section 3.1 reductions")
     ap.add_argument("--large-n64", action="store_true", help="add the n=64 partial 12-tree leg (exact vs Bloom, capped levels)")
     ap.add_argument("--large-cap-log2", type=int, default=29, help="log2 of the states-per-level cap of that leg")
+    ap.add_argument("--only-large", action="store_true",
+                    help="run only the n=64 leg and print its result (for profiling that workload alone)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.only_large:
+        print(json.dumps({"large_n64": large_leg(args.large_cap_log2)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the search over one graph "
@@ -574,7 +586,7 @@ def main():
         roofline["traffic_GBps"] = round(traffic / avg_launch_s / 1e9, 1)
         roofline["traffic_frac"] = round(traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)
     if not args.no_probe and ks > 0:
-        roofline["probe_reference"] = probe_reference(total["successors"] / ks)
+        roofline["probe_reference"] = probe_reference(total["successors"] / ks, total["unique"] / ks)
     out = {
         "metric": "(S,v) expansions/sec + graphs solved/sec (learned-k batched vs plain), exact",
         "value": total["expansions"] / elapsed,
