@@ -10,11 +10,18 @@ solves and nothing else.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
 
-Prints one JSON line.  Fields beyond the driver's contract:
+Prints one JSON line on stdout (progress of the longer legs goes to
+stderr).  Fields beyond the driver's contract:
   batch         graphs solved per second on 512 held-out graphs (n 20..32),
                 batched: plain ascending k, the learned start bound, and both
                 with the clique skip and disjoint-path edges of §3.1
                 (outside the timed region of `value`)
+  batch_n16_48  the 512-graph uneven batch with n 16..48 (seeds 3000+), each
+                level capped at 2^26 states: graphs solved per second, plain
+                against the learned start bound, with the unsolved graphs and
+                the level each reached
+  small_graphs  G(20, 0.3) solves, captured level loop against the
+                host-driven loop, with the oracle timed on the same graphs
   reductions    the bench solves again with those reductions: time per step
                 and expansions against the plain Listing 1 search
   roofline      the expansion kernel against HBM bandwidth, algorithmic bytes
@@ -295,7 +302,7 @@ def batch_config_leg(graphs, label: str, max_states: int, weights: str, reductio
                 exp += st["expansions"]
                 dec += st["decisions"]
                 print(json.dumps({"leg": label, "policy": name, "graphs_done": lo + len(a),
-                                  "seconds": round(dt, 1)}), flush=True)
+                                  "seconds": round(dt, 1)}), file=sys.stderr, flush=True)
         res[name] = (tws, status, per)
         o = _outcomes(graphs, tws, status, per)
         o["seconds"] = round(dt, 2)
@@ -327,7 +334,7 @@ def batch_config_leg(graphs, label: str, max_states: int, weights: str, reductio
                     if any(int(x) != 0 for x in b) or any(int(a[j]) != int(tp[both[lo + j]]) for j in range(len(a))):
                         raise RuntimeError(f"{label}: a solved graph changed on the second pass")
                     print(json.dumps({"leg": label, "solved_only": name, "graphs_done": lo + len(a),
-                                      "seconds": round(dt, 1)}), flush=True)
+                                      "seconds": round(dt, 1)}), file=sys.stderr, flush=True)
             out[f"solved_only_{name}"] = {"graphs": len(sub), "seconds": round(dt, 2),
                                           "graphs_per_s": round(len(sub) / dt, 2), "expansions": exp,
                                           "bounds_tried": dec}
@@ -342,7 +349,7 @@ def batch_config_leg(graphs, label: str, max_states: int, weights: str, reductio
             t0 = time.perf_counter()
             for q, t in enumerate(both):
                 if q % 256 == 255:
-                    print(json.dumps({"leg": label, "ceiling_graphs_done": q + 1}), flush=True)
+                    print(json.dumps({"leg": label, "ceiling_graphs_done": q + 1}), file=sys.stderr, flush=True)
                 lb = T.mmw(graphs[t])
                 if reductions:
                     lb = max(lb, len(T.reductions(graphs[t])[0]) - 1)
@@ -387,7 +394,7 @@ def large_leg(cap_log2: int = 29) -> dict:
                      "unique": st.get("unique"), "launches": st.get("launches"),
                      "kernel_seconds": round(ks, 3),
                      "kernel_expansions_per_s": st.get("expansions", 0) / ks if ks else None}
-        print(json.dumps({"leg": "large_n64", name: out[name]}), flush=True)
+        print(json.dumps({"leg": "large_n64", name: out[name]}), file=sys.stderr, flush=True)
     return out
 
 
@@ -507,7 +514,9 @@ def main():
     ap.add_argument("--mmw", action="store_true", help="add a single-graph leg with per-state minor-min-width pruning")
     ap.add_argument("--no-small", action="store_true", help="skip the G(20, 0.3) captured-loop leg")
     ap.add_argument("--batch-n16-48", action="store_true",
-                    help="add the 512-graph batch with n 16..48 (seeds 3000+), plain vs learned, per-level cap")
+                    help="the 512-graph batch with n 16..48 (seeds 3000+), plain vs learned, per-level cap "
+                         "(run by default; kept for older command lines)")
+    ap.add_argument("--no-batch-n16-48", action="store_true", help="skip the n 16..48 batch leg")
     ap.add_argument("--learned-n20-56", action="store_true",
                     help="add the 2,048 held-out graphs with n 20..56 (seeds 600000+), plain vs learned vs ceiling")
     ap.add_argument("--cap", type=int, default=1 << 26, help="states per level for the two legs above")
@@ -632,10 +641,11 @@ def main():
         out["batch"] = batch_leg()
     if args.large_n64:
         out["large_n64"] = large_leg(args.large_cap_log2)
-    if args.batch_n16_48 or args.learned_n20_56:
+    run_n16_48 = not args.no_batch_n16_48
+    if run_n16_48 or args.learned_n20_56:
         from paper_1709_09990_amd import graphs as G
         wts = WEIGHTS_N40_REDUCED if args.reduce_batches else WEIGHTS
-        if args.batch_n16_48:
+        if run_n16_48:
             out["batch_n16_48"] = batch_config_leg(G.workload_batch(512, seed0=3000, n_lo=16, n_hi=48),
                                                    "batch_n16_48", args.cap, wts, args.reduce_batches)
         if args.learned_n20_56:
