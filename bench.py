@@ -259,8 +259,57 @@ def _outcomes(graphs, tws, status, per) -> dict:
     return out
 
 
+def _oracle_treewidth(rows):
+    """One graph's treewidth by the oracle's level search (Listing 1), on one
+    core: a worker of the process pool below."""
+    import numpy as np
+    from oracle import oracle as O
+    r = np.asarray(rows, dtype=np.uint64)
+    return O.treewidth_bfs(r, O.mmw(r), threads=1)
+
+
+def _pool_ready(_):
+    return 0
+
+
+def oracle_batch_sample(graphs, base: dict, max_n: int = 26, count: int = 64) -> dict:
+    """The oracle on a bounded sample of a batch: its first `count` graphs with
+    n <= max_n, one graph per host core at a time (a process pool started
+    before the timed region), against the GPU's batched solve of the same
+    graphs with the leg's options.  Treewidths must agree."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_1709_09990_amd import tw as T
+    sample = [g for g in graphs if len(g) <= max_n][:count]
+    if not sample:
+        return {}
+    try:
+        cores = min(16, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        cores = min(16, os.cpu_count() or 1)
+    rows = [[int(x) for x in g] for g in sample]
+    # fresh interpreters (this process already holds the GPU); a worker that
+    # cannot start raises here instead of leaving the map waiting
+    with ProcessPoolExecutor(max_workers=cores, mp_context=multiprocessing.get_context("spawn")) as ex:
+        list(ex.map(_pool_ready, range(cores), timeout=120))
+        t0 = time.perf_counter()
+        want = list(ex.map(_oracle_treewidth, rows, timeout=300))
+        cpu_s = time.perf_counter() - t0
+    with T.Context(device=0, **base) as c:
+        c.solve_batch(sample[:4])
+        t0 = time.perf_counter()
+        tws, _, status, _ = c.solve_batch(sample)
+        gpu_s = time.perf_counter() - t0
+    if list(status) != [0] * len(sample) or [int(x) for x in tws] != want:
+        raise RuntimeError("oracle sample: the batched GPU solve disagrees with the oracle")
+    return {"graphs": len(sample), "n_max": max(len(g) for g in sample), "cores": cores, "kind": "oracle",
+            "oracle_seconds": round(cpu_s, 3), "oracle_graphs_per_s": round(len(sample) / cpu_s, 2),
+            "gpu_seconds": round(gpu_s, 4), "gpu_graphs_per_s": round(len(sample) / gpu_s, 2),
+            "sample": f"the first {len(sample)} graphs with n <= {max_n}, plain ascending search"}
+
+
 def batch_config_leg(graphs, label: str, max_states: int, weights: str, reductions: bool,
-                     ceiling: bool = False, per_call: int = 128) -> dict:
+                     ceiling: bool = False, per_call: int = 128, cpu: bool = False) -> dict:
     """Graphs solved per second, plain ascending bounds against the learned
     start bound, on one batch, each graph's levels capped at max_states
     states (a graph whose level would exceed the cap returns TW_ECAPACITY with
@@ -317,6 +366,8 @@ def batch_config_leg(graphs, label: str, max_states: int, weights: str, reductio
         raise RuntimeError(f"{label}: the learned start bound changed an answer")
     out["identical_on_both_solved"] = len(both)
     out["learned_speedup"] = round(out["learned"]["graphs_solved_per_s"] / out["plain"]["graphs_solved_per_s"], 3)
+    if cpu:
+        out["oracle_sample"] = oracle_batch_sample(graphs, base)
     if ceiling and len(both) < len(graphs):
         # the graphs both solve, again: graphs solved per second without the
         # time the capped graphs cost
@@ -647,11 +698,12 @@ def main():
         wts = WEIGHTS_N40_REDUCED if args.reduce_batches else WEIGHTS
         if run_n16_48:
             out["batch_n16_48"] = batch_config_leg(G.workload_batch(512, seed0=3000, n_lo=16, n_hi=48),
-                                                   "batch_n16_48", args.cap, wts, args.reduce_batches)
+                                                   "batch_n16_48", args.cap, wts, args.reduce_batches,
+                                                   cpu=not args.no_cpu)
         if args.learned_n20_56:
             out["learned_n20_56"] = batch_config_leg(G.workload_batch(2048, seed0=600000, n_lo=20, n_hi=56),
                                                      "learned_n20_56", args.cap, wts, args.reduce_batches,
-                                                     ceiling=True)
+                                                     ceiling=True, cpu=not args.no_cpu)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
         # the paper's CPU baseline is sequential: the same oracle on one core
