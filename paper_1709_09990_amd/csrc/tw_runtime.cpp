@@ -167,6 +167,7 @@ struct tw_ctx {
     uint64_t keep_budget = 1ull << 30;  // bytes of levels tw_solve keeps for the order
     bool no_capture = false; // set while a call must not create graphs or pinned memory
     std::vector<Captured *> captured;  // instantiated level loops, by graph shape
+    int batch_leave_blocks = 0; // persistent batch grid: blocks per CU left to concurrent single-graph work
     void *h_cap = nullptr;   // pinned host block for the captured loop's control and counters
 };
 
@@ -2155,7 +2156,10 @@ tw_status batch_launch(tw_ctx *c, const std::vector<Graph> &graphs, const std::v
     a.max_load = 0.85f;
     a.spin_limit = 8u * 1000u * 1000u;  // idle polls of up to ~4 us each: about half a minute
     a.nb = (uint32_t)B;
-    const unsigned grid = (unsigned)(c->cu_count * twk::batch_blocks_per_cu());
+    int per_cu = twk::batch_blocks_per_cu();
+    if (batch_schedule_of(c) == TW_BATCH_PERSISTENT && c->batch_leave_blocks)
+        per_cu = std::max(1, per_cu - c->batch_leave_blocks);  // a resident grid would leave no room
+    const unsigned grid = (unsigned)(c->cu_count * per_cu);
     a.nwaves = grid * (unsigned)twk::kBatchWavesPerBlock;
     if (c->opt.timing)
         HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
@@ -3023,7 +3027,15 @@ tw_status solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t *ou
         pool.cv.notify_all();
         ids.clear();
     };
+    const bool early = !single_ids.empty();
     enqueue(single_ids);
+    // single-graph work running beside the batch: the persistent grid leaves
+    // each CU room for two blocks of it (its waves stay resident otherwise)
+    struct LeaveRoom {
+        tw_ctx *c;
+        ~LeaveRoom() { c->batch_leave_blocks = 0; }
+    } leave_room{c};
+    c->batch_leave_blocks = early && !pool.ctxs.empty() ? 2 : 0;
 
     const size_t before = single_ids.size();
     st = batch_run(c, graphs, rp, lbs, k0s, arena_of, batch_ids, out_tw, out_orders, offs, out_status,
@@ -3049,6 +3061,7 @@ tw_status solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t *ou
         if (st != TW_OK)
             return st;
     }
+    c->batch_leave_blocks = 0;
     enqueue(single_ids);
     for (int t : single_ids) {
         GraphOutcome oc;
