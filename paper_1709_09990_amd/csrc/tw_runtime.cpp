@@ -3010,8 +3010,19 @@ tw_status solve_batch(tw_ctx *c, const tw_graph *gs, uint32_t count, int32_t *ou
             pool.ctxs.push_back(x);
         }
         pool.rs.resize(pool.ctxs.size());
-        for (size_t w = 0; w < pool.ctxs.size(); ++w)
-            pool.th.emplace_back(worker, w);
+        for (size_t w = 0; w < pool.ctxs.size(); ++w) {
+            try {
+                pool.th.emplace_back(worker, w);
+            } catch (...) {
+                break;  // no more threads: the workers started so far serve the queue
+            }
+        }
+        // a context without a thread is not kept (with none, this context
+        // solves the graphs itself)
+        while (pool.ctxs.size() > pool.th.size()) {
+            tw_ctx_destroy(pool.ctxs.back());
+            pool.ctxs.pop_back();
+        }
     };
     auto enqueue = [&](std::vector<int> &ids) {
         if (ids.empty())
