@@ -102,17 +102,20 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t z)
     return z ^ (z >> 33);
 }
 
-// Called by one lane: append a job for (g, level).
+// Called by one lane: append a job for (g, level).  In the persistent launch
+// the calling wave keeps the job's first chunk for itself (the cursor starts
+// at 1), so a level of one chunk goes on without waiting for another wave to
+// find it; returns the job's index + 1, or 0 when no job was made.
 template <bool C>
-__device__ void push_job(const BatchArgs &a, int g, int level, uint64_t begin, uint64_t count, int k, uint32_t tag,
-                         uint64_t out_base)
+__device__ uint64_t push_job(const BatchArgs &a, int g, int level, uint64_t begin, uint64_t count, int k,
+                             uint32_t tag, uint64_t out_base)
 {
     if (!a.jobs)
-        return;  // level rounds: the graph's level fields are the next round's work
+        return 0;  // level rounds: the graph's level fields are the next round's work
     const unsigned long long idx = atomicAdd(&a.q->tail, 1ull);
     if (idx >= a.q->capacity) {
         atomicOr(&a.q->abort, 1u);
-        return;
+        return 0;
     }
     BatchJob *j = &a.jobs[idx];
     stc<C>(&j->graph, (int32_t)g);
@@ -130,10 +133,12 @@ __device__ void push_job(const BatchArgs &a, int g, int level, uint64_t begin, u
     per = per < a.chunk ? a.chunk : (per > kMaxTask ? (a.chunk > kMaxTask ? a.chunk : kMaxTask) : per);
     stc<C>(&j->chunk, (uint32_t)per);
     const uint32_t nchunks = (uint32_t)((count + per - 1) / per);
+    stc<C>(&j->cursor, 1u);  // chunk 0 is the caller's
     // this job's fields, and the graph fields written before it, are complete
     // before ready shows
     drain();
     __hip_atomic_store(&j->ready, nchunks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (uint64_t)idx + 1;
 }
 
 // Whole wave, after a YES at bound G->k with G->L levels in the arena: follow
@@ -199,9 +204,10 @@ __device__ void set_bound_rows(BatchGraph *G, int k, int lane)
 }
 
 template <bool C>
-__device__ void start_bound(const BatchArgs &a, BatchGraph *G, int g, int k, int lane)
+__device__ uint64_t start_bound(const BatchArgs &a, BatchGraph *G, int g, int k, int lane)
 {
     set_bound_rows<C>(G, k, lane);
+    uint64_t pushed = 0;
     if (lane == 0) {
         const uint32_t tag = ldc<C>(&G->tag) + 1u;
         stc<C>(&G->k, (int32_t)k);
@@ -214,8 +220,9 @@ __device__ void start_bound(const BatchArgs &a, BatchGraph *G, int g, int k, int
         stc<C>(&G->level_off[0], (uint64_t)0);
         stc<C>(&G->level_off[1], (uint64_t)1);  // level 0 is the empty set (never read from the arena)
         // the job is published after every lane's row (the drain waits for the whole wave)
-        push_job<C>(a, g, 0, 0, 1, k, tag, 1);
+        pushed = push_job<C>(a, g, 0, 0, 1, k, tag, 1);
     }
+    return read_lane64(pushed, 0);
 }
 
 // Whole wave, after every chunk of (g, level) has finished.  Advances the
@@ -223,8 +230,10 @@ __device__ void start_bound(const BatchArgs &a, BatchGraph *G, int g, int k, int
 // lowers the upper side; the graph is done when they meet.  The starting
 // bound may be the minor-min-width bound (ascending search) or a prediction
 // (the search then moves down after a YES and up after a NO).
+// Returns the index + 1 of the job it published with its first chunk kept
+// (persistent launch), else 0.
 template <bool C>
-__device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_count, int lane)
+__device__ uint64_t finish_level(const BatchArgs &a, int g, int level, uint64_t in_count, int lane)
 {
     BatchGraph *G = &a.graphs[g];
     // the fields the whole wave needs, loaded back to back (one memory round
@@ -271,7 +280,7 @@ __device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_c
     }
     if (ovf || tag >= 0xFFFEu || next == G->fault_level) {
         graph_done<C>(a, G, kBatchFallback, lane);
-        return;
+        return 0;
     }
     if (cnt == 0) {
         // NO at bound k
@@ -282,21 +291,21 @@ __device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_c
             if (lane == 0)
                 stc<C>(&G->tw, (int32_t)best);
             graph_done<C>(a, G, kBatchDone, lane);
-        } else {
-            start_bound<C>(a, G, g, known_no + 1, lane);
+            return 0;
         }
-        return;
+        return start_bound<C>(a, G, g, known_no + 1, lane);
     }
     if (lane == 0)
         stc<C>(&G->level_off[next + 1], next_off + cnt);
     if (next < L) {
+        uint64_t pushed = 0;
         if (lane == 0) {
             stc<C>(&G->level, (int32_t)next);
             stc<C>(&G->tag, tag + 1u);
             stc<C>(&G->out_count, 0ull);
-            push_job<C>(a, g, next, next_off, cnt, k, tag + 1u, next_off + cnt);
+            pushed = push_job<C>(a, g, next, next_off, cnt, k, tag + 1u, next_off + cnt);
         }
-        return;
+        return read_lane64(pushed, 0);
     }
     // YES at bound k: keep its order, then certify or move down
     if (lane == 0)
@@ -310,9 +319,9 @@ __device__ void finish_level(const BatchArgs &a, int g, int level, uint64_t in_c
         if (lane == 0)
             stc<C>(&G->tw, (int32_t)k);
         graph_done<C>(a, G, kBatchDone, lane);
-    } else {
-        start_bound<C>(a, G, g, k - 1, lane);
+        return 0;
     }
+    return start_bound<C>(a, G, g, k - 1, lane);
 }
 
 // States [lo, hi) of level `level` of graph g (the level starts at arena
@@ -457,46 +466,53 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
     const uint32_t gw = blockIdx.x * kBatchWaves + (uint32_t)wv;
     uint32_t spins = 0;
     uint64_t seen_h = ~0ull, seen_t = ~0ull;
+    uint64_t kept = 0;  // job whose first chunk this wave kept when it published it (index + 1)
 
     for (;;) {
-        const uint64_t h = read_lane64(ld_relaxed(&a.q->head), 0);
-        uint64_t t = read_lane64(ld_relaxed(&a.q->tail), 0);
-        if (t > a.q->capacity)
-            t = a.q->capacity;
         BatchJob *J = nullptr;
         uint32_t c = 0, nchunks = 0;
-        if (h != seen_h || t != seen_t) {
-            const uint32_t span = t > h ? (uint32_t)(t - h < kJobWindow ? t - h : kJobWindow) : 0u;
-            bool unpublished = false;
-            for (uint32_t q = 0; q < span; ++q) {
-                const uint64_t jid = h + (gw + q) % span;
-                BatchJob *cand = &a.jobs[jid];
-                const uint32_t nc = first_lane32(ld_relaxed(&cand->ready));  // chunks, once published
-                if (nc == 0) {
-                    unpublished = true;
-                    continue;
-                }
-                // the job's fields are read only after it was seen published
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                if (first_lane32(ld_relaxed(&cand->cursor)) < nc) {
-                    uint32_t got = 0;
-                    if (lane == 0)
-                        got = atomicAdd(&cand->cursor, 1u);
-                    got = (uint32_t)__builtin_amdgcn_readlane((int)got, 0);
-                    if (got < nc) {
-                        J = cand;
-                        c = got;
-                        nchunks = nc;
-                        break;
+        if (kept) {
+            J = &a.jobs[kept - 1];
+            nchunks = first_lane32(ld_relaxed(&J->ready));
+            kept = 0;
+        } else {
+            const uint64_t h = read_lane64(ld_relaxed(&a.q->head), 0);
+            uint64_t t = read_lane64(ld_relaxed(&a.q->tail), 0);
+            if (t > a.q->capacity)
+                t = a.q->capacity;
+            if (h != seen_h || t != seen_t) {
+                const uint32_t span = t > h ? (uint32_t)(t - h < kJobWindow ? t - h : kJobWindow) : 0u;
+                bool unpublished = false;
+                for (uint32_t q = 0; q < span; ++q) {
+                    const uint64_t jid = h + (gw + q) % span;
+                    BatchJob *cand = &a.jobs[jid];
+                    const uint32_t nc = first_lane32(ld_relaxed(&cand->ready));  // chunks, once published
+                    if (nc == 0) {
+                        unpublished = true;
+                        continue;
                     }
+                    // the job's fields are read only after it was seen published
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    if (first_lane32(ld_relaxed(&cand->cursor)) < nc) {
+                        uint32_t got = 0;
+                        if (lane == 0)
+                            got = atomicAdd(&cand->cursor, 1u);
+                        got = (uint32_t)__builtin_amdgcn_readlane((int)got, 0);
+                        if (got < nc) {
+                            J = cand;
+                            c = got;
+                            nchunks = nc;
+                            break;
+                        }
+                    }
+                    // every chunk handed out: the head moves past it
+                    if (jid == h && lane == 0)
+                        atomicCAS(&a.q->head, (unsigned long long)h, (unsigned long long)(h + 1));
                 }
-                // every chunk handed out: the head moves past it
-                if (jid == h && lane == 0)
-                    atomicCAS(&a.q->head, (unsigned long long)h, (unsigned long long)(h + 1));
-            }
-            if (!J && !unpublished) {
-                seen_h = h;
-                seen_t = t;
+                if (!J && !unpublished) {
+                    seen_h = h;
+                    seen_t = t;
+                }
             }
         }
         if (!J) {
@@ -543,7 +559,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
         d = (uint32_t)__builtin_amdgcn_readlane((int)d, 0);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (d == nchunks)
-            finish_level<true>(a, g, level, count, lane);
+            kept = finish_level<true>(a, g, level, count, lane);
     }
 }
 
