@@ -2283,8 +2283,8 @@ tw_status batch_run(tw_ctx *c, const std::vector<Graph> &graphs, const std::vect
             tw_status s = batch_launch(c, graphs, reds, lbs, k0s, arenas, group, out_tw, out_orders, offs,
                                        out_status, single_ids, outcomes, rs, trace);
             if (s == TW_ENOMEM) {
-                // device memory taken meanwhile (the single-graph path may run
-                // concurrently on a second stream): these graphs go that way too
+                // device memory taken meanwhile (the single-graph workers run
+                // concurrently on their own streams): these graphs go that way too
                 single_ids.insert(single_ids.end(), group.begin(), group.end());
                 c->err.clear();
             } else if (s != TW_OK) {
@@ -2333,8 +2333,8 @@ bool read_weights(const char *path, std::vector<float> &params)
 //    the ascending search's start and arena: predictions there overshoot.
 //  - Admission: the arena of a batched graph is 16 x the predicted peak level
 //    (never below the default); a graph whose arena would exceed kArenaMax is
-//    sent to the single-graph path at once (where it runs beside the batch, on
-//    a second stream) instead of overflowing in the batch.
+//    sent to the single-graph path at once (where the worker contexts run it
+//    beside the batch) instead of overflowing in the batch.
 constexpr uint64_t kArenaMax = 1ull << 23;
 // largest graphs whose learned start is used (the committed networks were
 // trained on graphs of 16..30 and 16..40 vertices)
