@@ -218,9 +218,12 @@ tw_status tw_solve_noalloc(tw_ctx *ctx, const tw_graph *g, int32_t *out_tw, int3
  * expands the current level of every running graph, a second advances each
  * graph's level or bound); options.batch_schedule chooses.  Graphs whose
  * levels outgrow their arena get one more batched attempt with four times the
- * arena (level rounds), and then, like the others, the tw_solve path.  The
- * treewidths equal tw_solve's; each order is checked by fill-in to have
- * exactly that width (several orders may qualify).
+ * arena, and then, like the others, the tw_solve path, which runs on up to
+ * four worker contexts of its own (each with its own stream and host thread;
+ * none when options.workspace is given): those bound there from the start
+ * beside the batched search, the rest after it.  The treewidths equal
+ * tw_solve's; each order is checked by fill-in to have exactly that width
+ * (several orders may qualify).
  * With options.k_policy = TW_K_LEARNED each graph starts at the bound the
  * network predicts (clamped to [lower bound, n-2]) and gets an arena sized
  * from the predicted peak level; the search then certifies the answer exactly
