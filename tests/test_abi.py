@@ -129,8 +129,19 @@ def test_tree_decomposition_from_orders(oracle):
 def test_invalid_options_rejected_before_any_device_call():
     """tw_ctx_create validates the option enums before touching a device, so
     a bad value is TW_EINVAL even on a machine without a GPU."""
-    bad = [dict(dedup=7), dict(reductions=3), dict(batch_schedule=4), dict(mmw_prune=2), dict(mmw_prune=-1)]
+    bad = [dict(dedup=7), dict(reductions=3), dict(batch_schedule=3), dict(batch_schedule=-1),
+           dict(mmw_prune=2), dict(mmw_prune=-1)]
     for kw in bad:
         with pytest.raises(T.TwError) as e:
             T.Context(device=0, **kw)
         assert e.value.status == T.TW_EINVAL, kw
+
+
+def test_batch_schedule_values():
+    """The batch schedule enum: the automatic choice is 0, the zero a
+    zero-initialised options struct carries, and the binding's default."""
+    import inspect
+    assert (T.TW_BATCH_AUTO, T.TW_BATCH_ROUNDS, T.TW_BATCH_PERSISTENT) == (0, 1, 2)
+    assert inspect.signature(T.Context.__init__).parameters["batch_schedule"].default == T.TW_BATCH_AUTO
+    hdr = open(os.path.join(ROOT, "include", "tw.h")).read()
+    assert "enum { TW_BATCH_AUTO = 0, TW_BATCH_ROUNDS = 1, TW_BATCH_PERSISTENT = 2 };" in hdr
