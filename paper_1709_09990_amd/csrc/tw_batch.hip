@@ -47,12 +47,6 @@ constexpr uint64_t kKeyMask = (1ull << kBatchKeyBits) - 1;
 constexpr uint64_t kMaxTask = 1024;  // states per task, largest (unless the caller asks for more)
 
 template <typename T>
-__device__ __forceinline__ T ld_acquire(T *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <typename T>
 __device__ __forceinline__ T ld_relaxed(T *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -567,10 +561,9 @@ __global__ __launch_bounds__(kBatchBlock) void batch_kernel(BatchArgs a)
 // Level rounds.  One launch expands the current level of every running graph,
 // its chunks laid out by a prefix sum over the graphs; a second launch
 // advances every graph that ran a level (next level, next bound, or done).
-// The kernel boundaries order the levels, so no wave waits on another and no
-// cache maintenance runs inside a launch (on this multi-XCD part every
-// agent-scope acquire invalidates an XCD's L2 and every release writes it
-// back, which the persistent queue pays per task).
+// The kernel boundaries order the levels, so no wave waits on another and
+// every access is a plain one; the price is a launch pair and a small plan
+// launch per round, which the persistent queue does without.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint64_t level_count(const BatchArgs &a, uint32_t g)
